@@ -1,0 +1,309 @@
+"""Plain FP64 CPU oracle for the EOFA hot path (arXiv:1611.00298).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by
+the CPU-baseline leg of bench.py, never by the product package.  It shares
+no code with the GPU path.
+
+The heavy routines live in ``oracle.c`` (plain C99, OpenMP over sites);
+this module loads them with ctypes and exposes numpy-array functions on
+fields in the natural layout (see ``dwf_inputs``).  The molecular-dynamics
+update is written here in numpy.
+
+Parity status: every function is pinned by the CPU tests in
+``tests/test_oracle_pins.py`` against closed forms, determinant identities,
+brute-force dense linear algebra, the free-field dispersion relation, gauge
+covariance and finite differences.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Geom(C.Structure):
+    _fields_ = [("L", C.c_int * 4), ("Ls", C.c_int), ("antiperiodic_t", C.c_int),
+                ("M5", C.c_double), ("b5", C.c_double), ("c5", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = C.CDLL(_LIB)
+        P, D, I_, L_ = C.c_void_p, C.c_double, C.c_int, C.c_long
+        g = C.POINTER(Geom)
+        sigs = {
+            "orc_gamma": (None, [I_, P]),
+            "orc_wilson": (None, [g, P, P, P, I_, I_]),
+            "orc_L": (None, [g, D, D, I_, P, P]),
+            "orc_chiral_matrix": (I_, [g, I_, I_, D, P]),
+            "orc_apply_chiral": (I_, [g, I_, D, D, I_, P, P]),
+            "orc_ddwf": (None, [g, P, D, D, I_, P, P]),
+            "orc_deofa": (None, [g, P, D, D, P, P]),
+            "orc_g5r5": (None, [g, P, P]),
+            "orc_H": (None, [g, P, D, D, P, P]),
+            "orc_omega_k": (None, [g, D, D, P, P, P]),
+            "orc_schur": (None, [g, P, D, D, I_, P, P]),
+            "orc_solve_ddwf_eo": (I_, [g, P, D, D, P, P, D, I_, I_, P]),
+            "orc_solve_H": (I_, [g, P, D, D, P, P, D, I_, P]),
+            "orc_eofa_chi": (I_, [g, P, D, D, P, P, P, I_, D, I_, P]),
+            "orc_action": (None, [g, D, D, P, P, P, P, P]),
+            "orc_force": (None, [g, P, D, D, P, P, P, P, P, L_]),
+            "orc_ddwf_sites": (None, [g, P, D, D, I_, P, P, L_, P]),
+            "orc_schur_sites": (None, [g, P, D, D, I_, P, P, L_, P]),
+        }
+        for name, (res, args) in sigs.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+class Lattice:
+    """Geometry: L = (Lx, Ly, Lz, Lt), Ls, M5 and the Moebius scale alpha.
+
+    b5 = c + d = (alpha + 1)/2 and c5 = c - d = (alpha - 1)/2 with d = 1/2
+    (Section 2: c = alpha/2, d = 1/2)."""
+
+    def __init__(self, L, Ls, M5=1.8, alpha=2.0, antiperiodic_t=True):
+        self.L = tuple(int(v) for v in L)
+        self.Ls = int(Ls)
+        self.M5 = float(M5)
+        self.alpha = float(alpha)
+        self.b5 = (self.alpha + 1.0) / 2.0
+        self.c5 = (self.alpha - 1.0) / 2.0
+        self.antiperiodic_t = bool(antiperiodic_t)
+        self.g = Geom((C.c_int * 4)(*self.L), self.Ls, int(self.antiperiodic_t),
+                      self.M5, self.b5, self.c5)
+        Lx, Ly, Lz, Lt = self.L
+        self.V = Lx * Ly * Lz * Lt
+        self.shape4 = (Lt, Lz, Ly, Lx)
+        self.shape5 = (self.Ls, Lt, Lz, Ly, Lx, 4, 3)
+
+    @property
+    def gp(self):
+        return C.byref(self.g)
+
+    def zeros5(self):
+        return np.zeros(self.shape5, dtype=np.complex128)
+
+    def parity_mask(self):
+        """4D parity p = (x+y+z+t) mod 2 in the natural layout (t,z,y,x)."""
+        t, z, y, x = np.indices(self.shape4)
+        return (x + y + z + t) % 2
+
+
+def gamma(mu: int) -> np.ndarray:
+    out = np.zeros((4, 4), dtype=np.complex128)
+    lib().orc_gamma(mu, _p(out))
+    return out
+
+
+def wilson(lat: Lattice, U, psi, dagger=False):
+    """D_w (or D_w^dag) applied slice by slice to a 5D (or 4D) field."""
+    psi = _c128(psi)
+    nsl = psi.size // (lat.V * 12)
+    out = np.empty_like(psi)
+    lib().orc_wilson(lat.gp, _p(_c128(U)), _p(psi), _p(out), nsl, int(dagger))
+    return out
+
+
+def L_op(lat: Lattice, mp, mm, psi, transpose=False):
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_L(lat.gp, mp, mm, int(transpose), _p(psi), _p(out))
+    return out
+
+
+CHIRAL = {"L": 0, "dtilde": 1, "dtilde_inv": 2, "dperp": 3, "mee": 4, "mee_inv": 5}
+
+
+def chiral_matrix(lat: Lattice, which: str, plus: bool, m: float) -> np.ndarray:
+    A = np.zeros((lat.Ls, lat.Ls))
+    rc = lib().orc_chiral_matrix(lat.gp, CHIRAL[which], int(plus), m, _p(A))
+    if rc:
+        raise ArithmeticError("singular Ls x Ls matrix")
+    return A
+
+
+def apply_chiral(lat: Lattice, which: str, mp, mm, psi, transpose=False):
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    rc = lib().orc_apply_chiral(lat.gp, CHIRAL[which], mp, mm, int(transpose), _p(psi), _p(out))
+    if rc:
+        raise ArithmeticError("singular Ls x Ls matrix")
+    return out
+
+
+def ddwf(lat: Lattice, U, mp, mm, psi, dagger=False):
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_ddwf(lat.gp, _p(_c128(U)), mp, mm, int(dagger), _p(psi), _p(out))
+    return out
+
+
+def deofa(lat: Lattice, U, mp, mm, psi):
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_deofa(lat.gp, _p(_c128(U)), mp, mm, _p(psi), _p(out))
+    return out
+
+
+def g5r5(lat: Lattice, psi):
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_g5r5(lat.gp, _p(psi), _p(out))
+    return out
+
+
+def H_op(lat: Lattice, U, mp, mm, psi):
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_H(lat.gp, _p(_c128(U)), mp, mm, _p(psi), _p(out))
+    return out
+
+
+def omega_k(lat: Lattice, m1, m2):
+    om_m = np.zeros(lat.Ls)
+    om_p = np.zeros(lat.Ls)
+    k = np.zeros(1)
+    lib().orc_omega_k(lat.gp, m1, m2, _p(om_m), _p(om_p), _p(k))
+    return om_m, om_p, float(k[0])
+
+
+def schur(lat: Lattice, U, mp, mm, psi, dagger=False):
+    """Mhat (or Mhat^dag) on odd sites of a full-layout 5D field."""
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_schur(lat.gp, _p(_c128(U)), mp, mm, int(dagger), _p(psi), _p(out))
+    return out
+
+
+def solve_ddwf_eo(lat: Lattice, U, mp, mm, b, tol=1e-12, maxiter=10000, fixed=0):
+    """Even-odd CGNR solve of D_DWF y = b.  Returns (y, iters, |b - D y|/|b|)."""
+    b = _c128(b)
+    y = np.zeros_like(b)
+    res = np.zeros(1)
+    it = lib().orc_solve_ddwf_eo(lat.gp, _p(_c128(U)), mp, mm, _p(b), _p(y), tol, maxiter,
+                                 fixed, _p(res))
+    return y, it, float(res[0])
+
+
+def solve_H(lat: Lattice, U, mp, mm, v, tol=1e-12, maxiter=100000):
+    v = _c128(v)
+    chi = np.zeros_like(v)
+    res = np.zeros(1)
+    it = lib().orc_solve_H(lat.gp, _p(_c128(U)), mp, mm, _p(v), _p(chi), tol, maxiter, _p(res))
+    return chi, it, float(res[0])
+
+
+def eofa_chi(lat: Lattice, U, m1, m2, phi, method="cayley", tol=1e-12, maxiter=100000):
+    """(chi_L, chi_R, iters) of eq. (3.3)'s definitions."""
+    chiL = lat.zeros5()
+    chiR = lat.zeros5()
+    its = np.zeros(2, dtype=np.int32)
+    rc = lib().orc_eofa_chi(lat.gp, _p(_c128(U)), m1, m2, _p(_c128(phi)), _p(chiL), _p(chiR),
+                            0 if method == "direct" else 1, tol, maxiter, _p(its))
+    if rc:
+        raise RuntimeError("oracle solve did not converge")
+    return chiL, chiR, its
+
+
+def action(lat: Lattice, m1, m2, phi, chiL, chiR):
+    """(S, Im S, M_EOFA phi) of eq. (2.5)."""
+    S = np.zeros(2)
+    phi = _c128(phi)
+    M = np.empty_like(phi)
+    lib().orc_action(lat.gp, m1, m2, _p(phi), _p(_c128(chiL)), _p(_c128(chiR)), _p(S), _p(M))
+    return float(S[0]), float(S[1]), M
+
+
+def force(lat: Lattice, U, m1, m2, chiL, chiR, links=None, want_grad=True):
+    """Force F = sum_a T^a d^a S of eq. (3.3) and the gradient G.
+
+    links: None (all, arrays shaped like U) or an int array (n, 2) of
+    (mu, natural site index) pairs (arrays shaped (n, 3, 3))."""
+    U = _c128(U)
+    if links is None:
+        F = np.zeros_like(U)
+        G = np.zeros_like(U) if want_grad else None
+        lib().orc_force(lat.gp, _p(U), m1, m2, _p(_c128(chiL)), _p(_c128(chiR)), _p(F), _p(G),
+                        None, 0)
+    else:
+        lk = np.ascontiguousarray(links, dtype=np.int32)
+        n = lk.shape[0]
+        F = np.zeros((n, 3, 3), dtype=np.complex128)
+        G = np.zeros((n, 3, 3), dtype=np.complex128) if want_grad else None
+        lib().orc_force(lat.gp, _p(U), m1, m2, _p(_c128(chiL)), _p(_c128(chiR)), _p(F), _p(G),
+                        _p(lk), n)
+    return F, G
+
+
+def ddwf_sites(lat: Lattice, U, mp, mm, psi, sites, dagger=False):
+    """(D_DWF psi) at sampled (s, natural site) pairs; returns (n, 4, 3)."""
+    st = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.zeros((st.shape[0], 4, 3), dtype=np.complex128)
+    lib().orc_ddwf_sites(lat.gp, _p(_c128(U)), mp, mm, int(dagger), _p(_c128(psi)), _p(st),
+                         st.shape[0], _p(out))
+    return out
+
+
+def schur_sites(lat: Lattice, U, mp, mm, psi, sites, dagger=False):
+    """(Mhat psi) at sampled (s, odd natural site) pairs; returns (n, 4, 3)."""
+    st = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.zeros((st.shape[0], 4, 3), dtype=np.complex128)
+    lib().orc_schur_sites(lat.gp, _p(_c128(U)), mp, mm, int(dagger), _p(_c128(psi)), _p(st),
+                          st.shape[0], _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# molecular dynamics (Section 3: HMC) -- plain numpy
+# ---------------------------------------------------------------------------
+
+def expi_hermitian(Q: np.ndarray) -> np.ndarray:
+    """exp(i Q) for a stack of Hermitian matrices, by eigen-decomposition."""
+    Qh = 0.5 * (Q + np.swapaxes(Q.conj(), -1, -2))
+    w, v = np.linalg.eigh(Qh)
+    return np.einsum("...ij,...j,...kj->...ik", v, np.exp(1j * w), v.conj())
+
+
+def md_update(U, P, F, dt_p, dt_u):
+    """P <- P - dt_p F, then U <- exp(i dt_u P) U; returns (U, P)."""
+    P = P - dt_p * F
+    U = expi_hermitian(dt_u * P) @ U
+    return U, P
+
+
+def kinetic(P) -> float:
+    """sum over links of tr(P^2) = (1/2) sum_a (p^a)^2."""
+    return float((P * np.swapaxes(P, -1, -2)).sum().real)
