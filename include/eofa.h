@@ -1,0 +1,159 @@
+/*
+ * eofa.h -- C ABI of the MI355X (gfx950) EOFA hot-path library.
+ *
+ * Exact one-flavour algorithm for Moebius domain wall fermions, after
+ * D. Murphy, "Domain Wall Fermion Simulations with the Exact One-Flavor
+ * Algorithm", LATTICE 2016 (arXiv:1611.00298).
+ *
+ * Conventions (the paper leaves them open; every entry point uses these):
+ *   - lattice L = (Lx, Ly, Lz, Lt), every extent even; 4D site index
+ *     i = x + Lx*(y + Ly*(z + Lz*t)); V = Lx*Ly*Lz*Lt; s = 0..Ls-1.
+ *   - chiral gamma basis: gamma_k = [[0,-i sigma_k],[i sigma_k,0]],
+ *     gamma_t = [[0,1],[1,0]], gamma_5 = diag(1,1,-1,-1); P+ = spins {0,1}.
+ *   - D_w psi(x) = (4-M5) psi(x) - 1/2 sum_mu [(1-gamma_mu) U_mu(x) psi(x+mu)
+ *       + (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu)], periodic in space and
+ *     (optionally) antiperiodic in t.
+ *   - L = P+ L+(m+) + P- L-(m-): (L+ v)_s = v_{s-1}, (L+ v)_0 = -m+ v_{Ls-1};
+ *     (L- v)_s = v_{s+1}, (L- v)_{Ls-1} = -m- v_0.
+ *   - b5 = (alpha+1)/2 and c5 = (alpha-1)/2 are the paper's c+d and c-d
+ *     (Section 2: c = alpha/2, d = 1/2).
+ *   - D_DWF(m+, m-) = D_w (b5 + c5 L) + (1 - L)            (eq. (2.3))
+ *   - Dtilde = b5 + c5 L; D_EOFA = D_DWF Dtilde^-1;
+ *     H(m+, m-) = gamma_5 R_5 D_EOFA(m+, m-)               (Section 2)
+ *
+ * Memory: every pointer named *_dev is a device pointer on the GPU that is
+ * current when the context is created, C-contiguous complex128 (pairs of
+ * doubles, real first), owned by the caller.  The library never frees or
+ * keeps a caller pointer beyond the call.  Layouts (natural):
+ *   gauge  U[mu][t][z][y][x][a][b]            4*V*9 complex
+ *   4D     phi[t][z][y][x][spin][colour]      V*12 complex
+ *   5D     psi[s][t][z][y][x][spin][colour]   Ls*V*12 complex
+ * All work is enqueued on the stream given at context creation; calls
+ * that return scalars (S, kinetic energy, statistics) synchronise it.
+ *
+ * Errors: every int-returning call gives EOFA_OK (0) or a negative code;
+ * eofa_last_error() then holds a message for the calling thread.  No C++
+ * exception crosses this interface.
+ */
+#ifndef EOFA_H
+#define EOFA_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EOFA_OK       0
+#define EOFA_EINVAL  -1   /* bad argument: odd extent, Ls out of range, NULL, m1 > m2, N(m) <= 0 */
+#define EOFA_ENOMEM  -2   /* device allocation failed */
+#define EOFA_ENOCONV -3   /* solver hit maxiter; outputs and statistics are still written */
+#define EOFA_ENAN    -4   /* a reduction produced NaN or Inf */
+#define EOFA_EDEVICE -5   /* a HIP runtime call failed */
+
+typedef struct eofa_ctx eofa_ctx_t;
+
+typedef enum {
+    EOFA_FP64 = 0,   /* double everywhere */
+    EOFA_FP32 = 1,   /* float storage and arithmetic */
+    EOFA_FP16 = 2,   /* IEEE half storage with one float norm per 5D site, float arithmetic */
+    EOFA_BF16 = 3    /* bfloat16 storage, float arithmetic */
+} eofa_prec_t;
+
+typedef struct {
+    int L[4];            /* Lx, Ly, Lz, Lt; each even and >= 2 */
+    int Ls;              /* extent of the fifth dimension, 1 <= Ls <= 64 */
+    double M5;           /* domain-wall height (Wilson mass -M5) */
+    double alpha;        /* Moebius scale (Section 2); alpha = 1 is Shamir */
+    int antiperiodic_t;  /* 1: antiperiodic in t, 0: periodic */
+} eofa_geom_t;
+
+typedef struct {
+    double tol;            /* target true residual |b - D_DWF y| / |b| per system */
+    int maxiter;           /* limit on inner CG iterations per system */
+    eofa_prec_t inner;     /* EOFA_FP64: plain CGNR; else reliable-update mixed precision */
+    double reliable_delta; /* reliable update when |r| falls below delta * |r| at the last update */
+} eofa_solver_t;
+
+typedef struct {
+    int iters[2];            /* CG iterations for (chi_L, chi_R) */
+    int reliable_updates[2]; /* FP64 residual recomputations (mixed precision) */
+    double true_resid[2];    /* |b - D_DWF y| / |b| recomputed in FP64 at the end */
+    double seconds;          /* wall time of the call */
+    double flops;            /* operator flops executed (1320 per Wilson hop per 5D site,
+                                72 per bidiagonal 5D op, 144 per inverse 5D op) */
+} eofa_stats_t;
+
+/* Create a context for one lattice geometry and gauge field.
+ * U_dev: gauge field, natural layout (see above); copied and converted.
+ * stream: hipStream_t (NULL for the default stream); all work goes there.
+ * Returns EOFA_EINVAL for bad geometry, EOFA_ENOMEM, EOFA_EDEVICE. */
+int eofa_ctx_create(eofa_ctx_t **ctx, const eofa_geom_t *geom, const void *U_dev, void *stream);
+
+/* Free the context and every workspace it owns. NULL is allowed. */
+void eofa_ctx_destroy(eofa_ctx_t *ctx);
+
+/* Replace the gauge field (e.g. after a molecular-dynamics link update). */
+int eofa_ctx_update_gauge(eofa_ctx_t *ctx, const void *U_dev);
+
+/* Apply the Moebius domain-wall operator of eq. (2.3).
+ *   eo = 0: out = D_DWF(m+, m-) in  (dagger: D_DWF^dag), full 5D fields.
+ *   eo = 1: out = Mhat in on odd sites, the even-odd Schur complement
+ *           Mhat = M_oo - M_oe M_ee^-1 M_eo of Section 5.1 (dagger: Mhat^dag);
+ *           even sites of in are ignored and even sites of out are zero.
+ * prec: arithmetic/storage precision of the operator (input and output
+ * stay complex128).  in_dev/out_dev: 5D natural layout, may not alias. */
+int dwf_apply(eofa_ctx_t *ctx, double m_plus, double m_minus, int dagger, int eo,
+              eofa_prec_t prec, const void *in_dev, void *out_dev);
+
+/* EOFA solves, action and M_EOFA phi (eqs. (2.5), (3.3), (5.1)).
+ *   chi_L = H(m1, m1)^-1 Omega_- P_- phi,  chi_R = H(m1, m2)^-1 Omega_+ P_+ phi
+ * (H(m2) - Delta_+ P_+ = H(m+ = m1, m- = m2)), computed in the Cayley form
+ * chi = Dtilde D_DWF^-1 gamma_5 R_5 v (footnote of Section 5.1) with
+ * even-odd CGNR.  Omega_-(s) = (-c5/b5)^s, Omega_+ = R_5 Omega_-,
+ * k = (b5+c5) b5^(2Ls-2) (m2-m1) / (N(m1) N(m2)), N(m) = b5^Ls + m (-c5)^Ls.
+ *   phi_dev: 4D pseudofermion.  x0_L/x0_R: initial guesses for chi (NULL: 0).
+ *   chiL_dev/chiR_dev: 5D outputs.  Mphi_dev: 4D output M_EOFA phi (NULL: skip).
+ *   S_out: S = phi^dag M_EOFA phi (NULL: skip).  stats may be NULL.
+ * Requires m1 <= m2.  EOFA_ENOCONV leaves the best iterate in chi. */
+int eofa_solve(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
+               const void *x0_L_dev, const void *x0_R_dev, void *chiL_dev, void *chiR_dev,
+               void *Mphi_dev, double *S_out, const eofa_solver_t *solver, eofa_stats_t *stats);
+
+/* Pseudofermion force of eq. (3.3):
+ *   d^a_{x,mu} S = k chi_L^dag g5 R5 (d^a D_w) chi_L - k chi_R^dag g5 R5 (d^a D_w) chi_R,
+ * d^a the derivative along U_mu(x) -> exp(i eps T^a) U_mu(x), T^a = lambda^a/2.
+ *   F_dev: F_mu(x) = sum_a T^a d^a S (Hermitian traceless 3x3 per link,
+ *          gauge layout).  G_dev (NULL: skip): the complex-matrix gradient
+ *          with dS = Re tr(G^dag dU) for any complex dU (gauge layout).
+ *   chiL_dev/chiR_dev: solutions from eofa_solve; if either is NULL both
+ *          are recomputed from phi_dev with `solver` (stats filled).
+ * FP64 accumulation throughout. */
+int eofa_force(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
+               const void *chiL_dev, const void *chiR_dev, void *F_dev, void *G_dev,
+               const eofa_solver_t *solver, eofa_stats_t *stats);
+
+/* Molecular-dynamics update (HMC, Section 3), FP64, gauge layout:
+ *   P <- P - dt_p F   (skipped if F_dev is NULL or dt_p == 0)
+ *   U <- exp(i dt_u P) U  (skipped if dt_u == 0)
+ * then kinetic_out (NULL: skip) = sum over links tr(P^2).
+ * U_dev/P_dev are updated in place.  The context's own gauge copy is not
+ * touched: call eofa_ctx_update_gauge afterwards. */
+int eofa_md_update(eofa_ctx_t *ctx, void *U_dev, void *P_dev, const void *F_dev,
+                   double dt_p, double dt_u, double *kinetic_out);
+
+/* Per-kernel timing with HIP events on the context stream.
+ * eofa_timing_enable(ctx, 1) starts recording (and clears totals);
+ * eofa_timing_query synchronises and returns, for kernel class `name`
+ * ("hop" = the 5D hopping kernel in any precision, "hop64", "hop32",
+ * "hop16", "hopb16", "blas", "force"), the launch count, the summed
+ * duration in ms and the summed algorithmic bytes. */
+int eofa_timing_enable(eofa_ctx_t *ctx, int on);
+int eofa_timing_query(eofa_ctx_t *ctx, const char *name, long *count, double *ms, double *bytes);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *eofa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EOFA_H */

@@ -1,0 +1,852 @@
+// api.cpp -- C ABI, context and workspaces, and the EOFA solver drivers.
+//
+// The solver follows Section 5.1 of the paper: the EOFA systems (eq. (5.1)
+// with alpha_l in {0, -1}) are right-preconditioned into the Cayley form
+// (H^-1 v = Dtilde D_DWF^-1 gamma_5 R_5 v), even-odd preconditioned, and
+// solved by CGNR on the odd-site Schur complement
+//   Mhat = M_ee - Dh_oe Dtilde M_ee^-1 Dh_eo Dtilde
+// either in FP64 or with a reliable-update mixed-precision inner loop
+// (FP32, FP16+norm or BF16 storage; FP64 reductions, FP64 solution and FP64
+// residual recomputation).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "eofa.h"
+#include "internal.h"
+
+namespace eofa {
+hipError_t launch_hop(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
+hipError_t launch_pupdate(int prec, const void* z, const float* zn, void* p, float* pn, void* pt,
+                          float* ptn, const double* sc, int i_new, int i_old, int first, int Vh,
+                          int Ls, int NS, size_t N, double b5, double c5, double mp, double mm,
+                          int nblk, hipStream_t st);
+int blas_blocks(size_t n5);
+hipError_t launch_reduce(const double* partial, int n, double* out, int slot, hipStream_t st);
+hipError_t launch_xr_update(int prec, void* x, float* xn, const void* p, const float* pn, void* r,
+                            float* rn, const void* w, const float* wn, const double* sc, int i_num,
+                            int i_den, size_t n5, size_t N, double* partial, int nblk, hipStream_t st);
+hipError_t launch_norm2(int prec, const void* f, const float* fn, size_t n5, size_t N,
+                        double* partial, int nblk, hipStream_t st);
+hipError_t launch_convert(int pi, int po, const void* in, const float* inn, void* out, float* outn,
+                          size_t n5, size_t N, int nblk, hipStream_t st);
+hipError_t launch_accum_hi(int px, void* xhi, void* xlo, float* xlon, size_t n5, size_t N, int nblk,
+                           hipStream_t st);
+hipError_t launch_zero(int prec, void* f, float* fn, size_t n5, size_t N, int nblk, hipStream_t st);
+hipError_t launch_ingest_gauge(const void* U, void* G, int* nbr, const int L[4], int Ls, int aperiodic,
+                               hipStream_t st);
+hipError_t launch_gauge_convert(int po, const void* in, void* out, size_t n, hipStream_t st);
+hipError_t launch_nat5_to_dev(const void* nat, void* de, void* dodd, const int L[4], int Ls, size_t N,
+                              hipStream_t st);
+hipError_t launch_dev_to_nat5(void* nat, const void* de, const void* dodd, const int L[4], int Ls,
+                              size_t N, hipStream_t st);
+hipError_t launch_eofa_source(const void* phi, const double* om, void* bLe, void* bLo, void* bRe,
+                              void* bRo, const int L[4], int Ls, size_t N, hipStream_t st);
+int action_blocks(int V);
+hipError_t launch_eofa_action(const void* phi, const void* chiL, const void* chiR, const double* om,
+                              double k, void* Mphi, double* partial, int V, int Ls, hipStream_t st);
+hipError_t launch_force(const void* U, const void* chiL, const void* chiR, double k, void* F, void* G,
+                        const int L[4], int Ls, int aperiodic, hipStream_t st);
+int md_blocks(int nlink);
+hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
+                            double* partial, hipStream_t st);
+}  // namespace eofa
+
+using namespace eofa;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+    int code;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) {
+    g_err = msg;
+    throw Fail{code};
+}
+
+void hipchk(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) fail(EOFA_ENOMEM, std::string(what) + ": out of device memory");
+        fail(EOFA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+// one checkerboard half of a 5D field in device layout
+struct Half {
+    void* d = nullptr;
+    float* nrm = nullptr;
+    int prec = -1;
+};
+
+enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_NCLS };
+const char* cls_name[C_NCLS] = {"hop64", "hop32", "hop16", "hopb16", "blas", "force"};
+
+struct TimingRec {
+    int cls;
+    int ev;
+    double bytes;
+};
+
+}  // namespace
+
+struct eofa_ctx {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    int L[4] = {0, 0, 0, 0};
+    int Ls = 0, V = 0, Vh = 0, aperiodic = 1;
+    double M5 = 0, alpha = 0, b5 = 0, c5 = 0, beta0 = 0, beta1 = 0;
+    size_t n5 = 0, N = 0;
+    int NS = 0, nblk_hop = 0, nblk_blas = 0;
+    int* nbr = nullptr;
+    void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
+    void* U_nat = nullptr;
+    double* om = nullptr;
+    std::vector<double> om_h;
+    double* partial = nullptr;
+    size_t npartial = 0;
+    double* sc = nullptr;        // device scalar slots
+    double* pinned = nullptr;    // host mirror of the slots
+    std::map<std::string, Half> ws;
+    std::map<std::string, void*> raw;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> evpool;
+    std::vector<TimingRec> recs;
+    long t_count[C_NCLS] = {0};
+    double t_ms[C_NCLS] = {0}, t_bytes[C_NCLS] = {0};
+    double flops = 0;
+};
+
+namespace {
+
+enum Slot { S_WW = 0, S_ZZ0 = 1, S_ZZ1 = 2, S_RR = 3, S_B2 = 4, S_T0 = 5, S_T1 = 6, S_NSLOT = 16 };
+
+size_t half_bytes(const eofa_ctx* c, int prec) { return (size_t)16 * nblocks_of(prec) * c->N; }
+
+Half& ws(eofa_ctx* c, const std::string& name, int prec) {
+    std::string key = name + "#" + std::to_string(prec);
+    auto it = c->ws.find(key);
+    if (it != c->ws.end()) return it->second;
+    Half h;
+    h.prec = prec;
+    hipchk(hipMalloc(&h.d, half_bytes(c, prec)), "hipMalloc(field)");
+    hipchk(hipMemsetAsync(h.d, 0, half_bytes(c, prec), c->st), "hipMemset(field)");
+    if (prec == P16) {
+        hipchk(hipMalloc((void**)&h.nrm, sizeof(float) * c->N), "hipMalloc(norm)");
+        hipchk(hipMemsetAsync(h.nrm, 0, sizeof(float) * c->N, c->st), "hipMemset(norm)");
+    }
+    return c->ws[key] = h;
+}
+
+void* rawbuf(eofa_ctx* c, const std::string& name, size_t bytes) {
+    auto it = c->raw.find(name);
+    if (it != c->raw.end()) return it->second;
+    void* p = nullptr;
+    hipchk(hipMalloc(&p, bytes), "hipMalloc(buffer)");
+    return c->raw[name] = p;
+}
+
+void* gauge_of(eofa_ctx* c, int prec) {
+    if (!c->gauge[prec]) {
+        const size_t nc = (size_t)2 * 8 * 9 * c->Vh;
+        hipchk(hipMalloc(&c->gauge[prec], nc * complex_bytes(prec)), "hipMalloc(gauge)");
+        hipchk(launch_gauge_convert(prec, c->gauge[P64], c->gauge[prec], nc, c->st), "gauge convert");
+    }
+    return c->gauge[prec];
+}
+
+// ---- timing ---------------------------------------------------------------
+int timing_begin(eofa_ctx* c) {
+    if (!c->timing) return -1;
+    const int idx = (int)c->recs.size() * 2;
+    while ((int)c->evpool.size() < idx + 2) {
+        hipEvent_t e;
+        hipchk(hipEventCreate(&e), "hipEventCreate");
+        c->evpool.push_back(e);
+    }
+    hipchk(hipEventRecord(c->evpool[idx], c->st), "hipEventRecord");
+    return idx;
+}
+
+void timing_end(eofa_ctx* c, int idx, int cls, double bytes) {
+    if (idx < 0) return;
+    hipchk(hipEventRecord(c->evpool[idx + 1], c->st), "hipEventRecord");
+    c->recs.push_back({cls, idx, bytes});
+}
+
+void timing_collect(eofa_ctx* c) {
+    if (c->recs.empty()) return;
+    hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    for (auto& r : c->recs) {
+        float ms = 0;
+        hipchk(hipEventElapsedTime(&ms, c->evpool[r.ev], c->evpool[r.ev + 1]), "hipEventElapsedTime");
+        c->t_count[r.cls] += 1;
+        c->t_ms[r.cls] += ms;
+        c->t_bytes[r.cls] += r.bytes;
+    }
+    c->recs.clear();
+}
+
+// ---- operator pieces ---------------------------------------------------------
+const Op5 I5{0, 0, 0.0, 0.0};
+Op5 Dt(const eofa_ctx* c, int tr) { return Op5{1, tr, c->b5, c->c5}; }
+Op5 DtInv(const eofa_ctx* c, int tr) { return Op5{2, tr, c->b5, c->c5}; }
+Op5 Mee(const eofa_ctx* c, int tr) { return Op5{1, tr, c->beta0, c->beta1}; }
+Op5 MeeInv(const eofa_ctx* c, int tr) { return Op5{2, tr, c->beta0, c->beta1}; }
+
+double op_flops(const Op5& o) { return o.kind == 1 ? 72.0 : o.kind == 2 ? 144.0 : 0.0; }
+
+struct HopCall {
+    int prec = P64;
+    bool dag = false;
+    bool hop = true;
+    int par = 0;   // output parity
+    const Half* in = nullptr;
+    Half* out = nullptr;
+    const Half* aux = nullptr;
+    const Half* aux2 = nullptr;
+    Op5 A = I5, B = I5, C = I5;
+    double ch = 1.0, ca = 1.0, cr = 1.0;
+    double mp = 0, mm = 0;
+    double* partial = nullptr;
+};
+
+void run_hop(eofa_ctx* c, const HopCall& h) {
+    HopArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = h.in ? h.in->d : nullptr;
+    a.in_nrm = h.in ? h.in->nrm : nullptr;
+    a.out = h.out->d;
+    a.out_nrm = h.out->nrm;
+    a.aux = h.aux ? h.aux->d : nullptr;
+    a.aux_nrm = h.aux ? h.aux->nrm : nullptr;
+    a.aux2 = h.aux2 ? h.aux2->d : nullptr;
+    a.aux2_nrm = h.aux2 ? h.aux2->nrm : nullptr;
+    a.gauge = (const char*)gauge_of(c, h.prec) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(h.prec);
+    a.nbr = c->nbr + (size_t)h.par * 8 * c->Vh;
+    a.Vh = c->Vh;
+    a.Ls = c->Ls;
+    a.NS = c->NS;
+    a.N = c->N;
+    a.mp = h.mp;
+    a.mm = h.mm;
+    a.opA = h.A;
+    a.opB = h.B;
+    a.opC = h.C;
+    a.ch = h.ch;
+    a.ca = h.ca;
+    a.cr = h.cr;
+    a.partial = h.partial;
+    // bookkeeping: flops (fixed convention) and algorithmic bytes
+    double f = 0, nfields = 1;
+    if (h.hop) f += 1320.0 + op_flops(h.A), nfields += 1;
+    if (h.aux) f += op_flops(h.B) + (h.hop ? 24.0 : 0.0), nfields += 1;
+    if (h.aux2) f += 24.0, nfields += 1;
+    f += op_flops(h.C);
+    c->flops += f * (double)c->n5;
+    double bytes = nfields * spinor_bytes(h.prec) * (double)c->n5;
+    if (h.hop) bytes += 72.0 * complex_bytes(h.prec) * c->Vh;
+    const int ev = timing_begin(c);
+    hipchk(launch_hop(h.prec, h.dag, h.hop, a, c->nblk_hop, c->st), "hop kernel");
+    timing_end(c, ev, h.hop ? (int)h.prec : C_BLAS, bytes);
+}
+
+// local 5D op: out = C(ca * B(aux))
+void local_op(eofa_ctx* c, int prec, const Half& in, Half& out, Op5 B, Op5 C, double mp, double mm,
+              double ca = 1.0) {
+    HopCall h;
+    h.prec = prec;
+    h.hop = false;
+    h.aux = &in;
+    h.out = &out;
+    h.B = B;
+    h.C = C;
+    h.ca = ca;
+    h.mp = mp;
+    h.mm = mm;
+    run_hop(c, h);
+}
+
+void reduce(eofa_ctx* c, int n, int slot) {
+    hipchk(launch_reduce(c->partial, n, c->sc, slot, c->st), "reduce");
+}
+
+double read_slot(eofa_ctx* c, int slot) {
+    hipchk(hipMemcpyAsync(c->pinned + slot, c->sc + slot, sizeof(double), hipMemcpyDeviceToHost, c->st),
+           "hipMemcpy(scalar)");
+    hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    return c->pinned[slot];
+}
+
+double norm2(eofa_ctx* c, const Half& f, int slot) {
+    hipchk(launch_norm2(f.prec, f.d, f.nrm, c->n5, c->N, c->partial, c->nblk_blas, c->st), "norm2");
+    reduce(c, c->nblk_blas, slot);
+    return read_slot(c, slot);
+}
+
+void convert(eofa_ctx* c, const Half& in, Half& out) {
+    const int ev = timing_begin(c);
+    hipchk(launch_convert(in.prec, out.prec, in.d, in.nrm, out.d, out.nrm, c->n5, c->N, c->nblk_blas, c->st),
+           "convert");
+    timing_end(c, ev, C_BLAS, (double)c->n5 * (spinor_bytes(in.prec) + spinor_bytes(out.prec)));
+}
+
+void zero(eofa_ctx* c, Half& f) {
+    hipchk(launch_zero(f.prec, f.d, f.nrm, c->n5, c->N, c->nblk_blas, c->st), "zero");
+}
+
+// K1: tmp_e = M_ee^-1 Dtilde Dh_eo pt_o    (pt = Dtilde in)
+void schur_k1(eofa_ctx* c, int prec, const Half& pt, Half& tmp, double mp, double mm) {
+    HopCall h;
+    h.prec = prec; h.par = 0; h.in = &pt; h.out = &tmp;
+    h.A = Dt(c, 0); h.C = MeeInv(c, 0); h.mp = mp; h.mm = mm;
+    run_hop(c, h);
+}
+// K2: out_o = M_ee p_o - Dh_oe tmp_e   (+ |out|^2 partials)
+void schur_k2(eofa_ctx* c, int prec, const Half& tmp, const Half& p, Half& out, double mp, double mm,
+              double* partial) {
+    HopCall h;
+    h.prec = prec; h.par = 1; h.in = &tmp; h.out = &out; h.ch = -1.0;
+    h.aux = &p; h.B = Mee(c, 0); h.ca = 1.0; h.mp = mp; h.mm = mm; h.partial = partial;
+    run_hop(c, h);
+}
+// K3: tmp_e = M_ee^-dag Dtilde^dag Dh^dag_eo in_o
+void schur_k3(eofa_ctx* c, int prec, const Half& in, Half& tmp, double mp, double mm) {
+    HopCall h;
+    h.prec = prec; h.dag = true; h.par = 0; h.in = &in; h.out = &tmp;
+    h.A = Dt(c, 1); h.C = MeeInv(c, 1); h.mp = mp; h.mm = mm;
+    run_hop(c, h);
+}
+// K4: out_o = M_ee^dag in_o - Dtilde^dag Dh^dag_oe tmp_e   (+ partials)
+void schur_k4(eofa_ctx* c, int prec, const Half& tmp, const Half& in, Half& out, double mp, double mm,
+              double* partial) {
+    HopCall h;
+    h.prec = prec; h.dag = true; h.par = 1; h.in = &tmp; h.out = &out; h.A = Dt(c, 1); h.ch = -1.0;
+    h.aux = &in; h.B = Mee(c, 1); h.ca = 1.0; h.mp = mp; h.mm = mm; h.partial = partial;
+    run_hop(c, h);
+}
+
+void check_finite(double v, const char* what) {
+    if (!std::isfinite(v)) fail(EOFA_ENAN, std::string("non-finite ") + what);
+}
+
+struct SolveResult {
+    int iters = 0;
+    int reliable = 0;
+    bool converged = false;
+};
+
+// Solve Mhat x_o = bhat_o by CGNR, x_o holding the initial guess.
+// Stops when |bhat - Mhat x| <= thresh.  prec == P64: plain FP64 CGNR.
+// Otherwise: reliable-update mixed precision with an inner precision `prec`.
+SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half& x, bool guess,
+                       double thresh, int maxiter, int prec, double delta) {
+    SolveResult res;
+    const int nb = c->nblk_hop;
+    Half& tmp64 = ws(c, "tmp_e", P64);
+    Half& r64 = ws(c, "r", P64);
+    Half& xt64 = ws(c, "xt", P64);
+    // r = bhat - Mhat x
+    auto true_residual = [&](void) -> double {
+        HopCall h;
+        local_op(c, P64, x, xt64, Dt(c, 0), I5, mp, mm);
+        schur_k1(c, P64, xt64, tmp64, mp, mm);
+        h.prec = P64; h.par = 1; h.in = &tmp64; h.out = &r64; h.ch = 1.0;
+        h.aux = &x; h.B = Mee(c, 0); h.ca = -1.0; h.aux2 = &bhat; h.cr = 1.0;
+        h.mp = mp; h.mm = mm; h.partial = c->partial;
+        run_hop(c, h);
+        reduce(c, nb, S_RR);
+        return read_slot(c, S_RR);
+    };
+    double rr;
+    if (guess) {
+        rr = true_residual();
+    } else {
+        zero(c, x);
+        convert(c, bhat, r64);
+        rr = norm2(c, r64, S_RR);
+    }
+    check_finite(rr, "residual norm");
+    if (std::sqrt(rr) <= thresh) { res.converged = true; return res; }
+
+    const bool mixed = prec != P64;
+    const int px = mixed ? P32 : P64;
+    Half& r = mixed ? ws(c, "r_lo", prec) : r64;
+    Half& z = ws(c, "z", prec);
+    Half& p = ws(c, "p", prec);
+    Half& pt = ws(c, "pt", prec);
+    Half& w = ws(c, "w", prec);
+    Half& tmp = ws(c, "tmp_lo_e", prec);
+    Half& xl = mixed ? ws(c, "x_lo", px) : x;
+    if (mixed) {
+        convert(c, r64, r);
+        zero(c, xl);
+    }
+    int cur = S_ZZ0, nxt = S_ZZ1;
+    // z = Mhat^dag r ; p = z ; pt = Dtilde p
+    schur_k3(c, prec, r, tmp, mp, mm);
+    schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
+    reduce(c, nb, cur);
+    hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pt.d, pt.nrm, c->sc, cur, cur, 1, c->Vh, c->Ls,
+                          c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+    double rmax = std::sqrt(rr);
+    while (res.iters < maxiter) {
+        // w = Mhat p, |w|^2
+        schur_k1(c, prec, pt, tmp, mp, mm);
+        schur_k2(c, prec, tmp, p, w, mp, mm, c->partial);
+        reduce(c, nb, S_WW);
+        // x += alpha p, r -= alpha w, |r|^2
+        {
+            const int ev = timing_begin(c);
+            hipchk(launch_xr_update(prec, xl.d, xl.nrm, p.d, p.nrm, r.d, r.nrm, w.d, w.nrm, c->sc, cur,
+                                    S_WW, c->n5, c->N, c->partial, c->nblk_blas, c->st), "xr_update");
+            timing_end(c, ev, C_BLAS, (double)c->n5 * (2.0 * spinor_bytes(px) + 5.0 * spinor_bytes(prec)));
+            c->flops += 96.0 * (double)c->n5;
+        }
+        reduce(c, c->nblk_blas, S_RR);
+        res.iters++;
+        rr = read_slot(c, S_RR);
+        check_finite(rr, "residual norm");
+        const double rn = std::sqrt(rr);
+        if (mixed && (rn <= delta * rmax || rn <= thresh)) {
+            // reliable update: fold x_lo into x, recompute r in FP64
+            hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+            rr = true_residual();
+            check_finite(rr, "true residual");
+            res.reliable++;
+            rmax = std::sqrt(rr);
+            if (rmax <= thresh) { res.converged = true; break; }
+            convert(c, r64, r);
+        } else if (!mixed && rn <= thresh) {
+            res.converged = true;
+            break;
+        }
+        // z = Mhat^dag r, |z|^2 ; p = z + beta p
+        schur_k3(c, prec, r, tmp, mp, mm);
+        schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
+        reduce(c, nb, nxt);
+        hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pt.d, pt.nrm, c->sc, nxt, cur, 0, c->Vh,
+                              c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+        c->flops += 72.0 * (double)c->n5 + 48.0 * (double)c->n5;
+        std::swap(cur, nxt);
+    }
+    if (mixed && !res.converged)
+        hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+    return res;
+}
+
+struct CayleyOut {
+    int iters = 0, reliable = 0;
+    double true_resid = 0;
+    bool converged = false;
+};
+
+// Solve D_DWF(mp, mm) y = b (even-odd, Section 5.1), then chi = Dtilde y.
+// y_e/y_o hold an initial guess when `guess`.  Writes chi_e/chi_o.
+CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const Half& bo, Half& ye,
+                       Half& yo, bool guess, Half& chie, Half& chio, const eofa_solver_t& sp) {
+    CayleyOut out;
+    const int nb = c->nblk_hop;
+    // |b|^2
+    const double b2 = norm2(c, be, S_B2) + norm2(c, bo, S_B2);
+    check_finite(b2, "source norm");
+    if (b2 == 0.0) {
+        zero(c, ye); zero(c, yo); zero(c, chie); zero(c, chio);
+        out.converged = true;
+        return out;
+    }
+    const double bnorm = std::sqrt(b2);
+    // bhat_o = b_o - Dh_oe Dtilde M_ee^-1 b_e
+    Half& t = ws(c, "t_e", P64);
+    Half& bhat = ws(c, "bhat", P64);
+    local_op(c, P64, be, t, Dt(c, 0), MeeInv(c, 0), mp, mm);
+    {
+        HopCall h;
+        h.prec = P64; h.par = 1; h.in = &t; h.out = &bhat; h.ch = -1.0;
+        h.aux2 = &bo; h.cr = 1.0; h.mp = mp; h.mm = mm;
+        run_hop(c, h);
+    }
+    const int prec = sp.inner;
+    double thresh = 0.5 * sp.tol * bnorm;
+    bool have = guess;
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        SolveResult r = cgnr_schur(c, mp, mm, bhat, yo, have, thresh, sp.maxiter - out.iters, prec,
+                                   sp.reliable_delta > 0 ? sp.reliable_delta : 0.1);
+        out.iters += r.iters;
+        out.reliable += r.reliable;
+        // y_e = M_ee^-1 (b_e - Dh_eo Dtilde y_o)
+        Half& yt = ws(c, "xt", P64);
+        local_op(c, P64, yo, yt, Dt(c, 0), I5, mp, mm);
+        {
+            HopCall h;
+            h.prec = P64; h.par = 0; h.in = &yt; h.out = &ye; h.ch = -1.0;
+            h.aux2 = &be; h.cr = 1.0; h.C = MeeInv(c, 0); h.mp = mp; h.mm = mm;
+            run_hop(c, h);
+        }
+        // chi = Dtilde y
+        local_op(c, P64, ye, chie, Dt(c, 0), I5, mp, mm);
+        local_op(c, P64, yo, chio, Dt(c, 0), I5, mp, mm);
+        // true residual of the full system: b_p - M_ee y_p - Dh (Dtilde y)_pbar
+        Half& rt = ws(c, "rt", P64);
+        for (int par = 0; par < 2; ++par) {
+            HopCall h;
+            h.prec = P64; h.par = par; h.in = par ? &chie : &chio; h.out = &rt; h.ch = -1.0;
+            h.aux = par ? &yo : &ye; h.B = Mee(c, 0); h.ca = -1.0;
+            h.aux2 = par ? &bo : &be; h.cr = 1.0; h.mp = mp; h.mm = mm;
+            h.partial = c->partial + (size_t)par * nb;
+            run_hop(c, h);
+        }
+        reduce(c, 2 * nb, S_T0);
+        const double rr = read_slot(c, S_T0);
+        check_finite(rr, "true residual");
+        out.true_resid = std::sqrt(rr) / bnorm;
+        out.converged = out.true_resid <= sp.tol;
+        if (out.converged || !r.converged || out.iters >= sp.maxiter) break;
+        // the recursively updated residual drifted: tighten and continue from y
+        thresh *= 0.25 * sp.tol / out.true_resid;
+        have = true;
+    }
+    return out;
+}
+
+void validate_solver(const eofa_solver_t* sp) {
+    if (!sp) fail(EOFA_EINVAL, "solver parameters are NULL");
+    if (!(sp->tol > 0) || sp->maxiter <= 0) fail(EOFA_EINVAL, "solver tol must be > 0 and maxiter > 0");
+    if (sp->inner < EOFA_FP64 || sp->inner > EOFA_BF16) fail(EOFA_EINVAL, "unknown inner precision");
+}
+
+void omega_k(const eofa_ctx* c, double m1, double m2, double* k) {
+    const double N1 = std::pow(c->b5, c->Ls) + m1 * std::pow(-c->c5, c->Ls);
+    const double N2 = std::pow(c->b5, c->Ls) + m2 * std::pow(-c->c5, c->Ls);
+    if (!(N1 > 0) || !(N2 > 0)) fail(EOFA_EINVAL, "N(m) = b5^Ls + m (-c5)^Ls must be positive");
+    *k = (c->b5 + c->c5) * std::pow(c->b5, 2 * c->Ls - 2) * (m2 - m1) / (N1 * N2);
+}
+
+int solve_impl(eofa_ctx* c, double m1, double m2, const void* phi, const void* x0L, const void* x0R,
+               void* chiL, void* chiR, void* Mphi, double* S, const eofa_solver_t* sp,
+               eofa_stats_t* stats) {
+    if (!c || !phi || !chiL || !chiR) fail(EOFA_EINVAL, "NULL argument");
+    validate_solver(sp);
+    if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
+    double k;
+    omega_k(c, m1, m2, &k);
+    const auto t0 = std::chrono::steady_clock::now();
+    const double f0 = c->flops;
+    Half& bLe = ws(c, "bL_e", P64);
+    Half& bLo = ws(c, "bL_o", P64);
+    Half& bRe = ws(c, "bR_e", P64);
+    Half& bRo = ws(c, "bR_o", P64);
+    hipchk(launch_eofa_source(phi, c->om, bLe.d, bLo.d, bRe.d, bRo.d, c->L, c->Ls, c->N, c->st), "source");
+    Half& ye = ws(c, "y_e", P64);
+    Half& yo = ws(c, "y_o", P64);
+    Half& ce = ws(c, "chi_e", P64);
+    Half& co = ws(c, "chi_o", P64);
+    int status = EOFA_OK;
+    for (int sys = 0; sys < 2; ++sys) {
+        const double mp = m1, mm = sys == 0 ? m1 : m2;
+        const void* x0 = sys == 0 ? x0L : x0R;
+        if (x0) {   // y0 = Dtilde^-1 chi0
+            hipchk(launch_nat5_to_dev(x0, ce.d, co.d, c->L, c->Ls, c->N, c->st), "layout");
+            local_op(c, P64, ce, ye, I5, DtInv(c, 0), mp, mm);
+            local_op(c, P64, co, yo, I5, DtInv(c, 0), mp, mm);
+        }
+        CayleyOut o = solve_cayley(c, mp, mm, sys ? bRe : bLe, sys ? bRo : bLo, ye, yo, x0 != nullptr,
+                                   ce, co, *sp);
+        hipchk(launch_dev_to_nat5(sys ? chiR : chiL, ce.d, co.d, c->L, c->Ls, c->N, c->st), "layout");
+        if (stats) {
+            stats->iters[sys] = o.iters;
+            stats->reliable_updates[sys] = o.reliable;
+            stats->true_resid[sys] = o.true_resid;
+        }
+        if (!o.converged) status = EOFA_ENOCONV;
+    }
+    if (S || Mphi) {
+        const int nb = action_blocks(c->V);
+        hipchk(launch_eofa_action(phi, chiL, chiR, c->om, k, Mphi, c->partial, c->V, c->Ls, c->st), "action");
+        reduce(c, nb, S_T1);
+        const double s = read_slot(c, S_T1);
+        check_finite(s, "action");
+        if (S) *S = s;
+    }
+    hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    if (stats) {
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->flops = c->flops - f0;
+    }
+    if (status != EOFA_OK) g_err = "solver did not reach the requested true residual";
+    return status;
+}
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        g_err.clear();
+        return f();
+    } catch (const Fail& e) {
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return EOFA_EDEVICE;
+    } catch (...) {
+        g_err = "unknown error";
+        return EOFA_EDEVICE;
+    }
+}
+
+void free_ctx(eofa_ctx* c) {
+    if (!c) return;
+    if (c->st) hipStreamSynchronize(c->st);
+    for (auto& kv : c->ws) { hipFree(kv.second.d); if (kv.second.nrm) hipFree(kv.second.nrm); }
+    for (auto& kv : c->raw) hipFree(kv.second);
+    for (int p = 0; p < 4; ++p) if (c->gauge[p]) hipFree(c->gauge[p]);
+    if (c->nbr) hipFree(c->nbr);
+    if (c->U_nat) hipFree(c->U_nat);
+    if (c->om) hipFree(c->om);
+    if (c->partial) hipFree(c->partial);
+    if (c->sc) hipFree(c->sc);
+    if (c->pinned) hipHostFree(c->pinned);
+    for (auto e : c->evpool) hipEventDestroy(e);
+    delete c;
+}
+
+void load_gauge(eofa_ctx* c, const void* U) {
+    const size_t nb = (size_t)4 * c->V * 9 * 16;
+    hipchk(hipMemcpyAsync(c->U_nat, U, nb, hipMemcpyDeviceToDevice, c->st), "copy gauge");
+    hipchk(launch_ingest_gauge(c->U_nat, c->gauge[P64], c->nbr, c->L, c->Ls, c->aperiodic, c->st), "ingest");
+    const size_t nc = (size_t)2 * 8 * 9 * c->Vh;
+    for (int p = 1; p < 4; ++p)
+        if (c->gauge[p]) hipchk(launch_gauge_convert(p, c->gauge[P64], c->gauge[p], nc, c->st), "gauge convert");
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* eofa_last_error(void) { return g_err.c_str(); }
+
+int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void* stream) {
+    return guarded([&]() -> int {
+        if (!out || !g || !U) fail(EOFA_EINVAL, "NULL argument");
+        *out = nullptr;
+        for (int mu = 0; mu < 4; ++mu)
+            if (g->L[mu] < 2 || (g->L[mu] & 1)) fail(EOFA_EINVAL, "every lattice extent must be even and >= 2");
+        if (g->Ls < 1 || g->Ls > 64) fail(EOFA_EINVAL, "Ls must be in [1, 64]");
+        const double V = (double)g->L[0] * g->L[1] * g->L[2] * g->L[3];
+        if (V * g->Ls * 12 > 4.0e9 || V > 1.0e9) fail(EOFA_EINVAL, "lattice too large for 32-bit site indices");
+        eofa_ctx* c = new eofa_ctx();
+        try {
+            hipchk(hipGetDevice(&c->dev), "hipGetDevice");
+            c->st = (hipStream_t)stream;
+            for (int mu = 0; mu < 4; ++mu) c->L[mu] = g->L[mu];
+            c->Ls = g->Ls;
+            c->V = g->L[0] * g->L[1] * g->L[2] * g->L[3];
+            c->Vh = c->V / 2;
+            c->aperiodic = g->antiperiodic_t ? 1 : 0;
+            c->M5 = g->M5;
+            c->alpha = g->alpha;
+            c->b5 = 0.5 * (g->alpha + 1.0);
+            c->c5 = 0.5 * (g->alpha - 1.0);
+            c->beta0 = c->b5 * (4.0 - c->M5) + 1.0;
+            c->beta1 = c->c5 * (4.0 - c->M5) - 1.0;
+            if (c->b5 == 0.0 || c->beta0 == 0.0) fail(EOFA_EINVAL, "degenerate Moebius parameters");
+            c->n5 = (size_t)c->Vh * c->Ls;
+            c->N = (c->n5 + 255) / 256 * 256;
+            // workgroup: NS whole 4D sites x Ls; prefer a multiple of 64 work-items
+            int ns = 256 / c->Ls;
+            if (ns < 1) ns = 1;
+            int best = ns;
+            for (int q = ns; q >= 1; --q)
+                if ((q * c->Ls) % 64 == 0) { best = q; break; }
+            c->NS = best;
+            c->nblk_hop = (c->Vh + c->NS - 1) / c->NS;
+            c->nblk_blas = blas_blocks(c->n5);
+            size_t np = (size_t)2 * c->nblk_hop;
+            np = std::max(np, (size_t)action_blocks(c->V));
+            np = std::max(np, (size_t)md_blocks(4 * c->V));
+            np = std::max(np, (size_t)c->nblk_blas);
+            c->npartial = np;
+            hipchk(hipMalloc((void**)&c->partial, sizeof(double) * np), "hipMalloc(partial)");
+            hipchk(hipMalloc((void**)&c->sc, sizeof(double) * S_NSLOT), "hipMalloc(scalars)");
+            hipchk(hipMemsetAsync(c->sc, 0, sizeof(double) * S_NSLOT, c->st), "hipMemset");
+            hipchk(hipHostMalloc((void**)&c->pinned, sizeof(double) * S_NSLOT, 0), "hipHostMalloc");
+            hipchk(hipMalloc((void**)&c->nbr, sizeof(int) * 2 * 8 * c->Vh), "hipMalloc(nbr)");
+            hipchk(hipMalloc(&c->gauge[P64], (size_t)2 * 8 * 9 * c->Vh * 16), "hipMalloc(gauge)");
+            hipchk(hipMalloc(&c->U_nat, (size_t)4 * c->V * 9 * 16), "hipMalloc(U)");
+            c->om_h.resize(c->Ls);
+            for (int s = 0; s < c->Ls; ++s) c->om_h[s] = std::pow(-c->c5 / c->b5, s);
+            hipchk(hipMalloc((void**)&c->om, sizeof(double) * c->Ls), "hipMalloc(omega)");
+            hipchk(hipMemcpyAsync(c->om, c->om_h.data(), sizeof(double) * c->Ls, hipMemcpyHostToDevice, c->st),
+                   "copy omega");
+            load_gauge(c, U);
+            hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+        } catch (...) {
+            free_ctx(c);
+            throw;
+        }
+        *out = c;
+        return EOFA_OK;
+    });
+}
+
+void eofa_ctx_destroy(eofa_ctx_t* c) { free_ctx(c); }
+
+int eofa_ctx_update_gauge(eofa_ctx_t* c, const void* U) {
+    return guarded([&]() -> int {
+        if (!c || !U) fail(EOFA_EINVAL, "NULL argument");
+        load_gauge(c, U);
+        return EOFA_OK;
+    });
+}
+
+int dwf_apply(eofa_ctx_t* c, double mp, double mm, int dagger, int eo, eofa_prec_t prec,
+              const void* in, void* out) {
+    return guarded([&]() -> int {
+        if (!c || !in || !out) fail(EOFA_EINVAL, "NULL argument");
+        if (prec < EOFA_FP64 || prec > EOFA_BF16) fail(EOFA_EINVAL, "unknown precision");
+        if (eo != 0 && eo != 1) fail(EOFA_EINVAL, "eo must be 0 or 1");
+        if (in == out) fail(EOFA_EINVAL, "in and out may not alias");
+        const int P = prec;
+        Half& ie = ws(c, "ap_in_e", P64);
+        Half& io = ws(c, "ap_in_o", P64);
+        Half& oe = ws(c, "ap_out_e", P64);
+        Half& oo = ws(c, "ap_out_o", P64);
+        hipchk(launch_nat5_to_dev(in, ie.d, io.d, c->L, c->Ls, c->N, c->st), "layout");
+        Half* pie = &ie; Half* pio = &io; Half* poe = &oe; Half* poo = &oo;
+        if (P != P64) {
+            pie = &ws(c, "ap_in_e", P); pio = &ws(c, "ap_in_o", P);
+            poe = &ws(c, "ap_out_e", P); poo = &ws(c, "ap_out_o", P);
+            convert(c, ie, *pie);
+            convert(c, io, *pio);
+        }
+        Half& te = ws(c, "ap_t_e", P);
+        Half& to = ws(c, "ap_t_o", P);
+        if (eo == 0) {
+            for (int par = 0; par < 2; ++par) {
+                HopCall h;
+                h.prec = P; h.par = par; h.mp = mp; h.mm = mm;
+                h.out = par ? poo : poe;
+                h.aux = par ? pio : pie;
+                h.ca = 1.0; h.ch = 1.0;
+                if (!dagger) {
+                    // out_p = M_ee in_p + Dh (Dtilde in)_pbar
+                    Half& t = par ? te : to;
+                    local_op(c, P, par ? *pie : *pio, t, Dt(c, 0), I5, mp, mm);
+                    h.in = &t;
+                    h.B = Mee(c, 0);
+                } else {
+                    // out_p = M_ee^dag in_p + Dtilde^dag Dh^dag in_pbar
+                    h.dag = true;
+                    h.in = par ? pie : pio;
+                    h.A = Dt(c, 1);
+                    h.B = Mee(c, 1);
+                }
+                run_hop(c, h);
+            }
+        } else {
+            if (!dagger) {
+                local_op(c, P, *pio, to, Dt(c, 0), I5, mp, mm);
+                schur_k1(c, P, to, te, mp, mm);
+                schur_k2(c, P, te, *pio, *poo, mp, mm, nullptr);
+            } else {
+                schur_k3(c, P, *pio, te, mp, mm);
+                schur_k4(c, P, te, *pio, *poo, mp, mm, nullptr);
+            }
+            zero(c, *poe);
+        }
+        if (P != P64) {
+            convert(c, *poe, oe);
+            convert(c, *poo, oo);
+        }
+        hipchk(launch_dev_to_nat5(out, oe.d, oo.d, c->L, c->Ls, c->N, c->st), "layout");
+        return EOFA_OK;
+    });
+}
+
+int eofa_solve(eofa_ctx_t* c, double m1, double m2, const void* phi, const void* x0L, const void* x0R,
+               void* chiL, void* chiR, void* Mphi, double* S, const eofa_solver_t* sp,
+               eofa_stats_t* stats) {
+    return guarded([&]() -> int { return solve_impl(c, m1, m2, phi, x0L, x0R, chiL, chiR, Mphi, S, sp, stats); });
+}
+
+int eofa_force(eofa_ctx_t* c, double m1, double m2, const void* phi, const void* chiL, const void* chiR,
+               void* F, void* G, const eofa_solver_t* sp, eofa_stats_t* stats) {
+    return guarded([&]() -> int {
+        if (!c || !F) fail(EOFA_EINVAL, "NULL argument");
+        if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
+        double k;
+        omega_k(c, m1, m2, &k);
+        int status = EOFA_OK;
+        if (!chiL || !chiR) {
+            if (!phi) fail(EOFA_EINVAL, "phi is needed when chi is not given");
+            const size_t nb5 = (size_t)c->Ls * c->V * 12 * 16;
+            void* cl = rawbuf(c, "force_chiL", nb5);
+            void* cr = rawbuf(c, "force_chiR", nb5);
+            status = solve_impl(c, m1, m2, phi, nullptr, nullptr, cl, cr, nullptr, nullptr, sp, stats);
+            if (status != EOFA_OK && status != EOFA_ENOCONV) return status;
+            chiL = cl;
+            chiR = cr;
+        }
+        const int ev = timing_begin(c);
+        hipchk(launch_force(c->U_nat, chiL, chiR, k, F, G, c->L, c->Ls, c->aperiodic, c->st), "force");
+        timing_end(c, ev, C_FORCE,
+                   4.0 * c->V * c->Ls * 192.0 + 4.0 * c->V * 144.0 * (G ? 3.0 : 2.0));
+        hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+        return status;
+    });
+}
+
+int eofa_md_update(eofa_ctx_t* c, void* U, void* P, const void* F, double dt_p, double dt_u,
+                   double* kin) {
+    return guarded([&]() -> int {
+        if (!c || !U || !P) fail(EOFA_EINVAL, "NULL argument");
+        const int nlink = 4 * c->V;
+        hipchk(launch_md_update(U, P, F, dt_p, dt_u, nlink, kin ? c->partial : nullptr, c->st), "md update");
+        if (kin) {
+            reduce(c, md_blocks(nlink), S_T1);
+            *kin = read_slot(c, S_T1);
+        }
+        return EOFA_OK;
+    });
+}
+
+int eofa_timing_enable(eofa_ctx_t* c, int on) {
+    return guarded([&]() -> int {
+        if (!c) fail(EOFA_EINVAL, "NULL argument");
+        timing_collect(c);
+        c->timing = on != 0;
+        for (int k = 0; k < C_NCLS; ++k) { c->t_count[k] = 0; c->t_ms[k] = 0; c->t_bytes[k] = 0; }
+        return EOFA_OK;
+    });
+}
+
+int eofa_timing_query(eofa_ctx_t* c, const char* name, long* count, double* ms, double* bytes) {
+    return guarded([&]() -> int {
+        if (!c || !name) fail(EOFA_EINVAL, "NULL argument");
+        timing_collect(c);
+        long n = 0;
+        double t = 0, b = 0;
+        bool found = false;
+        for (int k = 0; k < C_NCLS; ++k) {
+            const bool hit = !strcmp(name, cls_name[k]) || (!strcmp(name, "hop") && k <= C_HOPB16);
+            if (hit) { n += c->t_count[k]; t += c->t_ms[k]; b += c->t_bytes[k]; found = true; }
+        }
+        if (!found) fail(EOFA_EINVAL, std::string("unknown kernel class ") + name);
+        if (count) *count = n;
+        if (ms) *ms = t;
+        if (bytes) *bytes = b;
+        return EOFA_OK;
+    });
+}
+
+}  // extern "C"

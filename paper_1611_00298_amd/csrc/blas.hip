@@ -1,0 +1,230 @@
+// blas.hip -- CG vector updates, FP64 reductions and precision conversion.
+//
+// Reductions are deterministic: every workgroup writes one FP64 partial
+// (wavefront xor-shuffle tree, then a fixed-order sum over wavefronts) and
+// a single-workgroup kernel sums the partials in a fixed order into a
+// device scalar slot.  CG scalars (alpha, beta) are formed on the device
+// from those slots, so no host round trip sits between the kernels.
+#include "internal.h"
+
+namespace eofa {
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// workgroup sum of x (fixed order), written by thread 0 to *dst
+__device__ __forceinline__ void block_store_sum(double x, double* dst) {
+    __shared__ double red[16];
+    x = wave_sum(x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) t += red[i];
+        *dst = t;
+    }
+}
+
+// out[slot] = sum of partial[0..n) (one workgroup of 1024)
+__global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ partial, int n,
+                                                 double* out, int slot) {
+    double t = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t += partial[i];
+    block_store_sum(t, out + slot);
+}
+
+// x += alpha p ; r -= alpha w ; partial |r|^2 ; alpha = sc[i_num] / sc[i_den]
+template <int P, int PX>
+__global__ void __launch_bounds__(256) k_xr_update(void* x, float* xn, const void* p, const float* pn,
+                                                   void* r, float* rn, const void* w, const float* wn,
+                                                   const double* sc, int i_num, int i_den, size_t n5,
+                                                   size_t N, double* partial) {
+    using A = typename PT<P>::A;
+    using AX = typename PT<PX>::A;
+    const double alpha_d = sc[i_num] / sc[i_den];
+    const A alpha = (A)alpha_d;
+    double acc = 0;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        A pv[24], wv[24], rv[24];
+        AX xv[24];
+        ld_spinor<P>(p, pn, N, n, pv);
+        ld_spinor<P>(w, wn, N, n, wv);
+        ld_spinor<P>(r, rn, N, n, rv);
+        ld_spinor<PX>(x, xn, N, n, xv);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            xv[k] += (AX)alpha_d * (AX)pv[k];
+            rv[k] -= alpha * wv[k];
+            acc += (double)rv[k] * (double)rv[k];
+        }
+        st_spinor<PX>(x, xn, N, n, xv);
+        st_spinor<P>(r, rn, N, n, rv);
+    }
+    block_store_sum(acc, partial + blockIdx.x);
+}
+
+// partial |f|^2
+template <int P>
+__global__ void __launch_bounds__(256) k_norm2(const void* f, const float* fn, size_t n5, size_t N,
+                                               double* partial) {
+    using A = typename PT<P>::A;
+    double acc = 0;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        A v[24];
+        ld_spinor<P>(f, fn, N, n, v);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc += (double)v[k] * (double)v[k];
+    }
+    block_store_sum(acc, partial + blockIdx.x);
+}
+
+// out = in, changing precision
+template <int PI, int PO>
+__global__ void __launch_bounds__(256) k_convert(const void* in, const float* inn, void* out,
+                                                 float* outn, size_t n5, size_t N) {
+    using AI = typename PT<PI>::A;
+    using AO = typename PT<PO>::A;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        AI v[24];
+        AO o[24];
+        ld_spinor<PI>(in, inn, N, n, v);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] = (AO)v[k];
+        st_spinor<PO>(out, outn, N, n, o);
+    }
+}
+
+// xhi += xlo ; xlo = 0
+template <int PX>
+__global__ void __launch_bounds__(256) k_accum_hi(void* xhi, void* xlo, float* xlon, size_t n5,
+                                                  size_t N) {
+    using AX = typename PT<PX>::A;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        double h[24];
+        AX l[24];
+        ld_spinor<P64>(xhi, nullptr, N, n, h);
+        ld_spinor<PX>(xlo, xlon, N, n, l);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) { h[k] += (double)l[k]; l[k] = 0; }
+        st_spinor<P64>(xhi, nullptr, N, n, h);
+        st_spinor<PX>(xlo, xlon, N, n, l);
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_zero(void* f, float* fn, size_t n5, size_t N) {
+    using A = typename PT<P>::A;
+    A v[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = 0;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x)
+        st_spinor<P>(f, fn, N, n, v);
+}
+
+// ---------------------------------------------------------------------------
+// launchers (grid: a fixed number of workgroups, grid-stride loops)
+// ---------------------------------------------------------------------------
+int blas_blocks(size_t n5) {
+    size_t b = (n5 + 255) / 256;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+hipError_t launch_reduce(const double* partial, int n, double* out, int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_xr_update(int prec, void* x, float* xn, const void* p, const float* pn, void* r,
+                            float* rn, const void* w, const float* wn, const double* sc, int i_num,
+                            int i_den, size_t n5, size_t N, double* partial, int nblk,
+                            hipStream_t st) {
+    switch (prec) {
+    case P64:
+        hipLaunchKernelGGL((k_xr_update<P64, P64>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
+                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
+        break;
+    case P32:
+        hipLaunchKernelGGL((k_xr_update<P32, P32>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
+                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
+        break;
+    case P16:
+        hipLaunchKernelGGL((k_xr_update<P16, P32>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
+                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
+        break;
+    case PB16:
+        hipLaunchKernelGGL((k_xr_update<PB16, P32>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
+                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(int prec, const void* f, const float* fn, size_t n5, size_t N,
+                        double* partial, int nblk, hipStream_t st) {
+    switch (prec) {
+    case P64: hipLaunchKernelGGL((k_norm2<P64>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N, partial); break;
+    case P32: hipLaunchKernelGGL((k_norm2<P32>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N, partial); break;
+    case P16: hipLaunchKernelGGL((k_norm2<P16>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N, partial); break;
+    case PB16: hipLaunchKernelGGL((k_norm2<PB16>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N, partial); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int PI>
+static hipError_t convert_from(int po, const void* in, const float* inn, void* out, float* outn,
+                               size_t n5, size_t N, int nblk, hipStream_t st) {
+    switch (po) {
+    case P64: hipLaunchKernelGGL((k_convert<PI, P64>), dim3(nblk), dim3(256), 0, st, in, inn, out, outn, n5, N); break;
+    case P32: hipLaunchKernelGGL((k_convert<PI, P32>), dim3(nblk), dim3(256), 0, st, in, inn, out, outn, n5, N); break;
+    case P16: hipLaunchKernelGGL((k_convert<PI, P16>), dim3(nblk), dim3(256), 0, st, in, inn, out, outn, n5, N); break;
+    case PB16: hipLaunchKernelGGL((k_convert<PI, PB16>), dim3(nblk), dim3(256), 0, st, in, inn, out, outn, n5, N); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int pi, int po, const void* in, const float* inn, void* out, float* outn,
+                          size_t n5, size_t N, int nblk, hipStream_t st) {
+    switch (pi) {
+    case P64: return convert_from<P64>(po, in, inn, out, outn, n5, N, nblk, st);
+    case P32: return convert_from<P32>(po, in, inn, out, outn, n5, N, nblk, st);
+    case P16: return convert_from<P16>(po, in, inn, out, outn, n5, N, nblk, st);
+    case PB16: return convert_from<PB16>(po, in, inn, out, outn, n5, N, nblk, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_accum_hi(int px, void* xhi, void* xlo, float* xlon, size_t n5, size_t N, int nblk,
+                           hipStream_t st) {
+    switch (px) {
+    case P64: hipLaunchKernelGGL((k_accum_hi<P64>), dim3(nblk), dim3(256), 0, st, xhi, xlo, xlon, n5, N); break;
+    case P32: hipLaunchKernelGGL((k_accum_hi<P32>), dim3(nblk), dim3(256), 0, st, xhi, xlo, xlon, n5, N); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(int prec, void* f, float* fn, size_t n5, size_t N, int nblk, hipStream_t st) {
+    switch (prec) {
+    case P64: hipLaunchKernelGGL((k_zero<P64>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N); break;
+    case P32: hipLaunchKernelGGL((k_zero<P32>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N); break;
+    case P16: hipLaunchKernelGGL((k_zero<P16>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N); break;
+    case PB16: hipLaunchKernelGGL((k_zero<PB16>), dim3(nblk), dim3(256), 0, st, f, fn, n5, N); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace eofa

@@ -1,0 +1,192 @@
+// internal.h -- shared declarations of the gfx950 EOFA library (GPU side only).
+//
+// Device layout of a 5D fermion field: one checkerboard ("half field") of
+// Vh = V/2 4D sites times Ls slices.  The 5D site index is n = cb*Ls + s
+// with cb = i/2 the checkerboard index of natural site i, so the Ls slices
+// of one 4D site are adjacent and a workgroup owns whole 4D sites.
+// Components are stored as 16-byte blocks, block-major ("SoA of 16 B"):
+//   FP64 : 12 blocks of double2 (one complex each)
+//   FP32 :  6 blocks of float4  (two complex each)
+//   FP16 :  3 blocks of 8 halves (four complex each) + one float norm per site
+//   BF16 :  3 blocks of 8 bfloat16
+// Block b of site n lives at base[b*N + n], N = padded number of 5D sites,
+// so the lanes of a wavefront read consecutive 16-byte words.
+//
+// Gauge links for output parity p are stored per output site, already
+// multiplied by -1/2 and by the boundary sign:
+//   d = 0..3 : -1/2 sigma U_mu(x)          (hop from x+mu)
+//   d = 4..7 : -1/2 sigma U_mu(x-mu)^dag   (hop from x-mu)
+// as [p][d][9][Vh] complex numbers of the field precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace eofa {
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
+
+template <int P> struct PT;
+template <> struct PT<P64>  { using A = double; static constexpr int NB = 12; static constexpr int CB = 16; };
+template <> struct PT<P32>  { using A = float;  static constexpr int NB = 6;  static constexpr int CB = 8; };
+template <> struct PT<P16>  { using A = float;  static constexpr int NB = 3;  static constexpr int CB = 4; };
+template <> struct PT<PB16> { using A = float;  static constexpr int NB = 3;  static constexpr int CB = 4; };
+
+inline int nblocks_of(int p) { return p == P64 ? 12 : p == P32 ? 6 : 3; }
+inline int complex_bytes(int p) { return p == P64 ? 16 : p == P32 ? 8 : 4; }
+// algorithmic bytes of one 5D spinor site
+inline int spinor_bytes(int p) { return p == P64 ? 192 : p == P32 ? 96 : p == P16 ? 52 : 48; }
+
+// ---------------------------------------------------------------------------
+// 16-bit conversions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float h2f(uint32_t bits16) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
+__device__ __forceinline__ uint32_t f2h(float f) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
+}
+__device__ __forceinline__ float b2f(uint32_t bits16) {
+    return __uint_as_float(bits16 << 16);
+}
+__device__ __forceinline__ uint32_t f2b(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// ---------------------------------------------------------------------------
+// spinor load / store (24 reals: complex c = spin*3 + colour, re = 2c)
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ void ld_spinor(const void* __restrict__ base, const float* __restrict__ nrm,
+                                          size_t N, size_t n, typename PT<P>::A (&v)[24]) {
+    if constexpr (P == P64) {
+        const double2* p = (const double2*)base;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) { double2 t = p[c * N + n]; v[2 * c] = t.x; v[2 * c + 1] = t.y; }
+    } else if constexpr (P == P32) {
+        const float4* p = (const float4*)base;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) {
+            float4 t = p[b * N + n];
+            v[4 * b] = t.x; v[4 * b + 1] = t.y; v[4 * b + 2] = t.z; v[4 * b + 3] = t.w;
+        }
+    } else {
+        const uint4* p = (const uint4*)base;
+        float sc = 1.0f;
+        if constexpr (P == P16) sc = nrm[n];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            uint4 t = p[b * N + n];
+            uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (P == P16) {
+                    v[8 * b + 2 * q] = h2f(w[q] & 0xffffu) * sc;
+                    v[8 * b + 2 * q + 1] = h2f(w[q] >> 16) * sc;
+                } else {
+                    v[8 * b + 2 * q] = b2f(w[q] & 0xffffu);
+                    v[8 * b + 2 * q + 1] = b2f(w[q] >> 16);
+                }
+            }
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void st_spinor(void* __restrict__ base, float* __restrict__ nrm,
+                                          size_t N, size_t n, const typename PT<P>::A (&v)[24]) {
+    if constexpr (P == P64) {
+        double2* p = (double2*)base;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c * N + n] = make_double2(v[2 * c], v[2 * c + 1]);
+    } else if constexpr (P == P32) {
+        float4* p = (float4*)base;
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+            p[b * N + n] = make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+    } else {
+        uint4* p = (uint4*)base;
+        float sc = 1.0f;
+        if constexpr (P == P16) {
+            float m = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
+            nrm[n] = m;
+            sc = m > 0.0f ? 1.0f / m : 0.0f;
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (P == P16)
+                    w[q] = f2h(v[8 * b + 2 * q] * sc) | (f2h(v[8 * b + 2 * q + 1] * sc) << 16);
+                else
+                    w[q] = f2b(v[8 * b + 2 * q]) | (f2b(v[8 * b + 2 * q + 1]) << 16);
+            }
+            p[b * N + n] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// links: complex k (row-major 3x3) of direction d at output site
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ void ld_link(const void* __restrict__ g, int d, int site, int Vh,
+                                        typename PT<P>::A (&u)[18]) {
+    const size_t off = (size_t)d * 9 * Vh + site;
+    if constexpr (P == P64) {
+        const double2* p = (const double2*)g;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { double2 t = p[off + (size_t)k * Vh]; u[2 * k] = t.x; u[2 * k + 1] = t.y; }
+    } else if constexpr (P == P32) {
+        const float2* p = (const float2*)g;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { float2 t = p[off + (size_t)k * Vh]; u[2 * k] = t.x; u[2 * k + 1] = t.y; }
+    } else {
+        const uint32_t* p = (const uint32_t*)g;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            uint32_t t = p[off + (size_t)k * Vh];
+            if constexpr (P == P16) { u[2 * k] = h2f(t & 0xffffu); u[2 * k + 1] = h2f(t >> 16); }
+            else { u[2 * k] = b2f(t & 0xffffu); u[2 * k + 1] = b2f(t >> 16); }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+
+// A 5D-local operator on the fifth dimension, per chirality:
+//   kind 0: identity, 1: a + b S, 2: (a + b S)^-1,
+// S = L (tr = 0) or L^T (tr = 1) with masses (m+, m-) of the launch.
+struct Op5 {
+    int kind;
+    int tr;
+    double a, b;
+};
+
+// out = C( ch * A(Dh in) + ca * B(aux) + cr * aux2 ), and optionally the
+// per-workgroup partial sums of |out|^2.  A and C act through LDS; B is a
+// bidiagonal (or identity) op read directly from aux.
+struct HopArgs {
+    const void* in; const float* in_nrm;
+    void* out; float* out_nrm;
+    const void* aux; const float* aux_nrm;
+    const void* aux2; const float* aux2_nrm;
+    const void* gauge;   // links of the output parity, [8][9][Vh]
+    const int* nbr;      // neighbour cb index of the output parity, [8][Vh]
+    int Vh, Ls, NS;
+    size_t N;
+    double mp, mm;
+    Op5 opA, opB, opC;
+    double ch, ca, cr;
+    double* partial;
+};
+
+}  // namespace eofa

@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/eofa.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "eofa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_lists_the_boundary():
+    names = declared_functions()
+    for required in ("dwf_apply", "eofa_solve", "eofa_force", "eofa_ctx_create",
+                     "eofa_ctx_destroy", "eofa_ctx_update_gauge", "eofa_md_update",
+                     "eofa_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1611_00298_amd import _lib
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == declared_functions()
+
+
+def _geom(L=(4, 4, 4, 4), Ls=8):
+    from paper_1611_00298_amd._lib import Geom
+    return Geom((C.c_int * 4)(*L), Ls, 1.8, 2.0, 1)
+
+
+@pytest.mark.parametrize("L,Ls", [((3, 4, 4, 4), 8), ((4, 4, 4, 0), 8), ((4, 4, 4, 4), 0),
+                                  ((4, 4, 4, 4), 65)])
+def test_bad_geometry_is_rejected_on_the_host(L, Ls):
+    from paper_1611_00298_amd import _lib
+    lib = _lib.load()
+    h = C.c_void_p()
+    g = _geom(L, Ls)
+    dummy = C.c_void_p(1)   # never dereferenced: validation fails first
+    rc = lib.eofa_ctx_create(C.byref(h), C.byref(g), dummy, None)
+    assert rc == _lib.EOFA_EINVAL
+    assert h.value is None
+    assert lib.eofa_last_error().decode() != ""
+
+
+def test_null_arguments_are_rejected():
+    from paper_1611_00298_amd import _lib
+    lib = _lib.load()
+    g = _geom()
+    assert lib.eofa_ctx_create(None, C.byref(g), C.c_void_p(1), None) == _lib.EOFA_EINVAL
+    assert lib.dwf_apply(None, 0.1, 0.1, 0, 0, 0, None, None) == _lib.EOFA_EINVAL
+    sp = _lib.Solver(1e-10, 100, 0, 0.1)
+    assert lib.eofa_solve(None, 0.1, 0.2, None, None, None, None, None, None, None,
+                          C.byref(sp), None) == _lib.EOFA_EINVAL
+    assert lib.eofa_force(None, 0.1, 0.2, None, None, None, None, None, C.byref(sp),
+                          None) == _lib.EOFA_EINVAL
+    assert lib.eofa_md_update(None, None, None, None, 0.0, 0.0, None) == _lib.EOFA_EINVAL
+    lib.eofa_ctx_destroy(None)
+
+
+def test_product_path_does_not_touch_the_oracle():
+    """The product package must not import or load the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_1611_00298_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "liboracle" not in txt, f

@@ -1,0 +1,78 @@
+"""GPU parity of the Moebius operator (eq. (2.3)) and its even-odd Schur
+complement (Section 5.1) against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import dwf_inputs as din
+import oracle
+from helpers import PREC_TOL, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# (L, Ls, alpha, antiperiodic): C1 shape, ragged workgroup tails, odd Ls,
+# Shamir and alpha = 4, periodic time
+CASES = [
+    ((4, 4, 4, 4), 8, 2.0, True),
+    ((4, 2, 6, 4), 5, 2.0, True),
+    ((2, 4, 2, 6), 3, 4.0, True),
+    ((4, 4, 2, 2), 16, 1.0, False),
+    ((2, 2, 4, 4), 24, 2.0, True),
+    ((6, 2, 2, 2), 1, 2.0, True),
+]
+MASSES = [(0.04, 0.04), (0.0362, 1.0)]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"L{'x'.join(map(str, c[0]))}_Ls{c[1]}_a{c[2]}")
+def setup(request):
+    from paper_1611_00298_amd import Context
+    L, Ls, alpha, ap = request.param
+    U = din.random_gauge(L, 0.4, 11)
+    psi = din.gaussian_5d(L, Ls, 12)
+    lat = oracle.Lattice(L, Ls, M5=1.8, alpha=alpha, antiperiodic_t=ap)
+    ctx = Context(L, Ls, to_dev(U), M5=1.8, alpha=alpha, antiperiodic_t=ap)
+    yield lat, U, psi, ctx
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("dagger", [False, True])
+@pytest.mark.parametrize("masses", MASSES)
+def test_ddwf_parity(setup, prec, dagger, masses):
+    lat, U, psi, ctx = setup
+    mp, mm = masses
+    out = ctx.dwf_apply(to_dev(psi), mp, mm, dagger=dagger, prec=prec).cpu().numpy()
+    ref = oracle.ddwf(lat, U, mp, mm, psi, dagger=dagger)
+    assert rel(out, ref) < PREC_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("dagger", [False, True])
+@pytest.mark.parametrize("masses", MASSES)
+def test_schur_parity(setup, prec, dagger, masses):
+    lat, U, psi, ctx = setup
+    mp, mm = masses
+    out = ctx.dwf_apply(to_dev(psi), mp, mm, dagger=dagger, eo=True, prec=prec).cpu().numpy()
+    ref = oracle.schur(lat, U, mp, mm, psi, dagger=dagger)
+    even = (lat.parity_mask() == 0)[None, ..., None, None]
+    assert np.abs(out * even).max() == 0.0
+    assert rel(out, ref) < PREC_TOL[prec]
+
+
+def test_adjoint_identity_gpu(setup):
+    lat, U, psi, ctx = setup
+    x = din.gaussian_5d(lat.L, lat.Ls, 21)
+    y = din.gaussian_5d(lat.L, lat.Ls, 22)
+    odd = (lat.parity_mask() == 1)[None, ..., None, None]
+    for eo in (False, True):
+        xx, yy = (x * odd, y * odd) if eo else (x, y)
+        Dy = ctx.dwf_apply(to_dev(yy), 0.1, 0.5, eo=eo).cpu().numpy()
+        Ddx = ctx.dwf_apply(to_dev(xx), 0.1, 0.5, dagger=True, eo=eo).cpu().numpy()
+        lhs, rhs = np.vdot(xx, Dy), np.vdot(Ddx, yy)
+        assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_deterministic(setup):
+    lat, U, psi, ctx = setup
+    a = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, eo=True).cpu().numpy()
+    b = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, eo=True).cpu().numpy()
+    assert np.array_equal(a, b)

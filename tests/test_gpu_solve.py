@@ -1,0 +1,175 @@
+"""GPU EOFA solves (Cayley form + even-odd CGNR, Section 5.1), action
+(eq. (2.5)), force (eq. (3.3)) and MD update against the CPU oracle."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import dwf_inputs as din
+import oracle
+from helpers import rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+C1 = din.preset("c1")
+
+
+def sources(lat, phi, m1, m2):
+    """v_L = Omega_- P_- phi, v_R = Omega_+ P_+ phi (eq. (3.3) definitions)."""
+    om_m, om_p, k = oracle.omega_k(lat, m1, m2)
+    vL, vR = lat.zeros5(), lat.zeros5()
+    vL[..., 2:, :] = om_m[:, None, None, None, None, None, None] * phi[None, ..., 2:, :]
+    vR[..., :2, :] = om_p[:, None, None, None, None, None, None] * phi[None, ..., :2, :]
+    return vL, vR, k
+
+
+@pytest.fixture(scope="module")
+def c1():
+    from paper_1611_00298_amd import Context
+    L, Ls = C1["L"], C1["Ls"]
+    U = din.random_gauge(L, C1["eps"], C1["seed_gauge"])
+    phi = din.gaussian_4d(L, C1["seed_phi"])
+    lat = oracle.Lattice(L, Ls, M5=C1["M5"], alpha=C1["alpha"])
+    ctx = Context(L, Ls, to_dev(U), M5=C1["M5"], alpha=C1["alpha"])
+    # oracle solutions to tight tolerance (Cayley + even-odd, pinned against the direct solve)
+    chiL, chiR, _ = oracle.eofa_chi(lat, U, C1["m1"], C1["m2"], phi, tol=1e-13)
+    S, _, M = oracle.action(lat, C1["m1"], C1["m2"], phi, chiL, chiR)
+    yield dict(lat=lat, U=U, phi=phi, ctx=ctx, chiL=chiL, chiR=chiR, S=S, M=M,
+               m1=C1["m1"], m2=C1["m2"])
+    ctx.close()
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "fp16", "bf16"])
+def test_solve_c1(c1, inner):
+    lat, U, phi, ctx = c1["lat"], c1["U"], c1["phi"], c1["ctx"]
+    m1, m2 = c1["m1"], c1["m2"]
+    chiL, chiR, Mphi, S, st = ctx.eofa_solve(to_dev(phi), m1, m2, tol=1e-10, inner=inner)
+    chiL, chiR, Mphi = chiL.cpu().numpy(), chiR.cpu().numpy(), Mphi.cpu().numpy()
+    assert st["converged"]
+    vL, vR, k = sources(lat, phi, m1, m2)
+    # the oracle recomputes the true residual of the H systems (definition level)
+    resL = rel(oracle.H_op(lat, U, m1, m1, chiL), vL)
+    resR = rel(oracle.H_op(lat, U, m1, m2, chiR), vR)
+    assert resL <= 1e-10 and resR <= 1e-10, (resL, resR, st)
+    # the GPU's own FP64 true residual agrees with the oracle's recomputation
+    assert st["true_resid"][0] <= 1e-10 and st["true_resid"][1] <= 1e-10
+    assert abs(st["true_resid"][0] - resL) <= 0.05 * resL + 1e-14
+    # solution and action against the tightly solved oracle
+    assert rel(chiL, c1["chiL"]) < 1e-8 and rel(chiR, c1["chiR"]) < 1e-8
+    assert abs(S - c1["S"]) <= 1e-10 * abs(c1["S"])
+    # action kernel parity on the GPU's chi
+    S2, _, M2 = oracle.action(lat, m1, m2, phi, chiL, chiR)
+    assert abs(S - S2) <= 1e-13 * abs(S2)
+    assert rel(Mphi, M2) < 1e-13
+    if inner != "fp64":
+        assert st["reliable_updates"][0] >= 1
+
+
+@pytest.mark.parametrize("n", [1, 5, 30])
+def test_fixed_iterations_match_oracle(c1, n):
+    """Same CGNR recurrences on both sides: N iterations from zero."""
+    lat, U, phi, ctx = c1["lat"], c1["U"], c1["phi"], c1["ctx"]
+    m1, m2 = c1["m1"], c1["m2"]
+    chiL, chiR, _, _, st = ctx.eofa_solve(to_dev(phi), m1, m2, tol=1e-30, maxiter=n,
+                                          allow_noconv=True)
+    assert st["iters"] == [n, n] and not st["converged"]
+    vL, vR, _ = sources(lat, phi, m1, m2)
+    for v, mm, chi in ((vL, m1, chiL), (vR, m2, chiR)):
+        b = oracle.g5r5(lat, v)
+        y, it, _ = oracle.solve_ddwf_eo(lat, U, m1, mm, b, fixed=n)
+        ref = oracle.apply_chiral(lat, "dtilde", m1, mm, y)
+        assert rel(chi.cpu().numpy(), ref) < 1e-12
+
+
+def test_initial_guess(c1):
+    lat, U, phi, ctx = c1["lat"], c1["U"], c1["phi"], c1["ctx"]
+    m1, m2 = c1["m1"], c1["m2"]
+    x0 = (to_dev(c1["chiL"]), to_dev(c1["chiR"]))
+    _, _, _, S, st = ctx.eofa_solve(to_dev(phi), m1, m2, x0=x0)
+    assert st["iters"][0] <= 2 and st["iters"][1] <= 2
+    assert abs(S - c1["S"]) <= 1e-10 * abs(c1["S"])
+    _, _, _, _, st0 = ctx.eofa_solve(to_dev(phi), m1, m2)
+    g = din.gaussian_5d(lat.L, lat.Ls, 5)
+    x0 = (to_dev(c1["chiL"] + 1e-4 * g), to_dev(c1["chiR"] + 1e-4 * g))
+    _, _, _, S, st = ctx.eofa_solve(to_dev(phi), m1, m2, x0=x0)
+    assert st["converged"] and st["iters"][0] < st0["iters"][0]
+
+
+def test_equal_masses(c1):
+    lat, phi, ctx = c1["lat"], c1["phi"], c1["ctx"]
+    _, _, Mphi, S, st = ctx.eofa_solve(to_dev(phi), 0.3, 0.3)
+    assert S == pytest.approx(np.vdot(phi, phi).real, rel=1e-14)
+    assert np.array_equal(Mphi.cpu().numpy(), phi)
+
+
+def test_error_paths(c1):
+    from paper_1611_00298_amd import EOFAError
+    from paper_1611_00298_amd._lib import EOFA_EINVAL, EOFA_ENAN
+    phi, ctx = c1["phi"], c1["ctx"]
+    with pytest.raises(EOFAError) as e:
+        ctx.eofa_solve(to_dev(phi), 0.5, 0.1)
+    assert e.value.code == EOFA_EINVAL
+    bad = phi.copy()
+    bad[0, 0, 0, 0, 2, 1] = np.nan
+    with pytest.raises(EOFAError) as e:
+        ctx.eofa_solve(to_dev(bad), 0.04, 1.0)
+    assert e.value.code == EOFA_ENAN
+    # maxiter reached: statistics are still filled
+    _, _, _, _, st = ctx.eofa_solve(to_dev(phi), 0.04, 1.0, maxiter=3, allow_noconv=True)
+    assert not st["converged"] and st["iters"][0] == 3 and st["true_resid"][0] > 1e-10
+
+
+def test_force_parity(c1):
+    lat, U, ctx = c1["lat"], c1["U"], c1["ctx"]
+    m1, m2 = c1["m1"], c1["m2"]
+    chiL, chiR = c1["chiL"], c1["chiR"]
+    F, G, _ = ctx.eofa_force(m1, m2, chiL=to_dev(chiL), chiR=to_dev(chiR), want_grad=True)
+    Fr, Gr = oracle.force(lat, U, m1, m2, chiL, chiR)
+    assert np.abs(F.cpu().numpy() - Fr).max() <= 1e-12 * np.abs(Fr).max()
+    assert np.abs(G.cpu().numpy() - Gr).max() <= 1e-12 * np.abs(Gr).max()
+
+
+def test_force_with_internal_solve(c1):
+    lat, U, phi, ctx = c1["lat"], c1["U"], c1["phi"], c1["ctx"]
+    m1, m2 = c1["m1"], c1["m2"]
+    F, _, st = ctx.eofa_force(m1, m2, phi=to_dev(phi), tol=1e-12)
+    Fr, _ = oracle.force(lat, U, m1, m2, c1["chiL"], c1["chiR"], want_grad=False)
+    assert np.abs(F.cpu().numpy() - Fr).max() <= 1e-8 * np.abs(Fr).max()
+    assert st["iters"][0] > 0
+
+
+def test_force_finite_difference_su3(c1):
+    """eq. (3.3) against central differences of S under U -> exp(i d T^a) U."""
+    from paper_1611_00298_amd import Context
+    lat, U, phi = c1["lat"], c1["U"], c1["phi"]
+    m1, m2 = c1["m1"], c1["m2"]
+    T = din.gell_mann() / 2
+    d = 1e-5
+    with Context(lat.L, lat.Ls, to_dev(U), M5=lat.M5, alpha=lat.alpha) as ctx:
+        F, _, _ = ctx.eofa_force(m1, m2, phi=to_dev(phi), tol=1e-13)
+        F = F.cpu().numpy()
+        rng = np.random.default_rng(7)
+        for _ in range(6):
+            mu = int(rng.integers(4))
+            site = tuple(int(rng.integers(n)) for n in lat.shape4)
+            a = int(rng.integers(8))
+            vals = []
+            for sgn in (1, -1):
+                Up = U.copy()
+                Up[(mu,) + site] = scipy.linalg.expm(sgn * 1j * d * T[a]) @ U[(mu,) + site]
+                ctx.update_gauge(to_dev(Up))
+                vals.append(ctx.eofa_solve(to_dev(phi), m1, m2, tol=1e-13, want_mphi=False)[3])
+            fd = (vals[0] - vals[1]) / (2 * d)
+            an = 2 * np.trace(T[a] @ F[(mu,) + site]).real
+            assert an == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_md_update(c1):
+    lat, U, ctx = c1["lat"], c1["U"], c1["ctx"]
+    P = din.gaussian_momenta(lat.L, 9)
+    F = din.gaussian_momenta(lat.L, 10)
+    Ud, Pd = to_dev(U), to_dev(P)
+    kin = ctx.md_update(Ud, Pd, to_dev(F), dt_p=0.05, dt_u=0.1)
+    Ur, Pr = oracle.md_update(U, P, F, 0.05, 0.1)
+    assert np.abs(Pd.cpu().numpy() - Pr).max() < 1e-15
+    assert np.abs(Ud.cpu().numpy() - Ur).max() < 1e-13
+    assert kin == pytest.approx(oracle.kinetic(Pr), rel=1e-13)
