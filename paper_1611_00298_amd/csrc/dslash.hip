@@ -77,20 +77,26 @@ __device__ __forceinline__ void reconstruct(const A (&u)[12], A (&acc)[24]) {
     }
 }
 
-// u(spin j) = link * h(spin j), link row major 3x3 complex
+// u(spin j) = link * h(spin j), link row major 3x3 complex; written as
+// explicit fused multiply-add chains (two FMAs per real term)
 template <typename A>
 __device__ __forceinline__ void su3_mul(const A (&U)[18], const A (&h)[12], A (&u)[12]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            A re = 0, im = 0;
+            const A* hj = &h[6 * j];
+            const A* Ua = &U[6 * a];
+            A re = Ua[0] * hj[0];
+            A im = Ua[0] * hj[1];
+            re = fmadd(-Ua[1], hj[1], re);
+            im = fmadd(Ua[1], hj[0], im);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const A ur = U[2 * (3 * a + b)], ui = U[2 * (3 * a + b) + 1];
-                const A hr = h[6 * j + 2 * b], hi = h[6 * j + 2 * b + 1];
-                re += ur * hr - ui * hi;
-                im += ur * hi + ui * hr;
+            for (int b = 1; b < 3; ++b) {
+                re = fmadd(Ua[2 * b], hj[2 * b], re);
+                re = fmadd(-Ua[2 * b + 1], hj[2 * b + 1], re);
+                im = fmadd(Ua[2 * b], hj[2 * b + 1], im);
+                im = fmadd(Ua[2 * b + 1], hj[2 * b], im);
             }
             u[6 * j + 2 * a] = re;
             u[6 * j + 2 * a + 1] = im;
@@ -105,9 +111,18 @@ __device__ __forceinline__ void hop_dir(const HopArgs& a, int site, int s,
     constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
     const int nb = a.nbr[(size_t)D * a.Vh + site];
     A psi[24];
-    ld_spinor<P>(a.in, a.in_nrm, a.N, (size_t)nb * a.Ls + s, psi);
     A h[12];
-    project<MU, SG>(psi, h);
+    if constexpr (P == P16 || P == PB16) {
+        const float sc = ld_spinor_raw<P>(a.in, a.in_nrm, a.N, (size_t)nb * a.Ls + s, psi);
+        project<MU, SG>(psi, h);
+        if constexpr (P == P16) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) h[k] *= sc;
+        }
+    } else {
+        ld_spinor<P>(a.in, a.in_nrm, a.N, (size_t)nb * a.Ls + s, psi);
+        project<MU, SG>(psi, h);
+    }
     A U[18];
     ld_link<P>(a.gauge, D, site, a.Vh, U);
     A u[12];
@@ -224,7 +239,7 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 }
 
 template <int P, bool DAG, bool HOP>
-__global__ void __launch_bounds__(512) k_hop(const HopArgs a) {
+__global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
     using A = typename PT<P>::A;
     extern __shared__ unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
@@ -234,7 +249,8 @@ __global__ void __launch_bounds__(512) k_hop(const HopArgs a) {
     const int Ls = a.Ls;
     const int sl = tid / Ls;
     const int s = tid - sl * Ls;
-    const int site = blockIdx.x * a.NS + sl;
+    const int lb = xcd_block(gridDim.x);
+    const int site = (a.order ? a.order[lb] : lb) * a.NS + sl;
     const bool active = site < a.Vh;
     const size_t n = (size_t)site * Ls + s;
     const A mp = (A)a.mp, mm = (A)a.mm;
@@ -297,7 +313,7 @@ __global__ void __launch_bounds__(512) k_hop(const HopArgs a) {
             for (int k = 0; k < 24; ++k) x += (double)v[k] * (double)v[k];
         }
         x = block_sum(x, red);
-        if (tid == 0) a.partial[blockIdx.x] = x;
+        if (tid == 0) a.partial[blockIdx.x] = x;   // order-independent slot
     }
 }
 
@@ -307,7 +323,7 @@ __global__ void __launch_bounds__(512) k_hop(const HopArgs a) {
 // the first call), pt <- Dtilde p = (b5 + c5 L) p.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void __launch_bounds__(512) k_pupdate(const void* z, const float* z_nrm, void* p,
+__global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_nrm, void* p,
                                                  float* p_nrm, void* pt, float* pt_nrm,
                                                  const double* sc, int i_new, int i_old, int first,
                                                  int Vh, int Ls, int NS, size_t N, double b5,
@@ -319,7 +335,7 @@ __global__ void __launch_bounds__(512) k_pupdate(const void* z, const float* z_n
     const int tid = threadIdx.x;
     const int sl = tid / Ls;
     const int s = tid - sl * Ls;
-    const int site = blockIdx.x * NS + sl;
+    const int site = xcd_block(gridDim.x) * NS + sl;
     const bool active = site < Vh;
     const size_t n = (size_t)site * Ls + s;
     A v[24];

@@ -38,6 +38,9 @@ inline int complex_bytes(int p) { return p == P64 ? 16 : p == P32 ? 8 : 4; }
 // algorithmic bytes of one 5D spinor site
 inline int spinor_bytes(int p) { return p == P64 ? 192 : p == P32 ? 96 : p == P16 ? 52 : 48; }
 
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // ---------------------------------------------------------------------------
 // 16-bit conversions
 // ---------------------------------------------------------------------------
@@ -59,27 +62,40 @@ __device__ __forceinline__ uint32_t f2b(float f) {   // round to nearest even
 // ---------------------------------------------------------------------------
 // spinor load / store (24 reals: complex c = spin*3 + colour, re = 2c)
 // ---------------------------------------------------------------------------
+// Field accesses use a uniform (scalar) base per 16-byte block plus a
+// 32-bit byte offset per lane, so the loads can use SGPR-base addressing.
+template <typename T>
+__device__ __forceinline__ const T& at(const void* base, size_t blk_bytes, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + blk_bytes + off);
+}
+template <typename T>
+__device__ __forceinline__ T& at_mut(void* base, size_t blk_bytes, uint32_t off) {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + blk_bytes + off);
+}
+
 template <int P>
 __device__ __forceinline__ void ld_spinor(const void* __restrict__ base, const float* __restrict__ nrm,
                                           size_t N, size_t n, typename PT<P>::A (&v)[24]) {
+    const uint32_t off = (uint32_t)n * 16u;
+    const size_t bb = N * 16;
     if constexpr (P == P64) {
-        const double2* p = (const double2*)base;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) { double2 t = p[c * N + n]; v[2 * c] = t.x; v[2 * c + 1] = t.y; }
+        for (int c = 0; c < 12; ++c) {
+            const double2 t = at<double2>(base, c * bb, off);
+            v[2 * c] = t.x; v[2 * c + 1] = t.y;
+        }
     } else if constexpr (P == P32) {
-        const float4* p = (const float4*)base;
 #pragma unroll
         for (int b = 0; b < 6; ++b) {
-            float4 t = p[b * N + n];
+            const float4 t = at<float4>(base, b * bb, off);
             v[4 * b] = t.x; v[4 * b + 1] = t.y; v[4 * b + 2] = t.z; v[4 * b + 3] = t.w;
         }
     } else {
-        const uint4* p = (const uint4*)base;
         float sc = 1.0f;
         if constexpr (P == P16) sc = nrm[n];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            uint4 t = p[b * N + n];
+            const uint4 t = at<uint4>(base, b * bb, off);
             uint32_t w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -98,17 +114,16 @@ __device__ __forceinline__ void ld_spinor(const void* __restrict__ base, const f
 template <int P>
 __device__ __forceinline__ void st_spinor(void* __restrict__ base, float* __restrict__ nrm,
                                           size_t N, size_t n, const typename PT<P>::A (&v)[24]) {
+    const uint32_t off = (uint32_t)n * 16u;
+    const size_t bb = N * 16;
     if constexpr (P == P64) {
-        double2* p = (double2*)base;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) p[c * N + n] = make_double2(v[2 * c], v[2 * c + 1]);
+        for (int c = 0; c < 12; ++c) at_mut<double2>(base, c * bb, off) = make_double2(v[2 * c], v[2 * c + 1]);
     } else if constexpr (P == P32) {
-        float4* p = (float4*)base;
 #pragma unroll
         for (int b = 0; b < 6; ++b)
-            p[b * N + n] = make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+            at_mut<float4>(base, b * bb, off) = make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
     } else {
-        uint4* p = (uint4*)base;
         float sc = 1.0f;
         if constexpr (P == P16) {
             float m = 0.0f;
@@ -127,35 +142,77 @@ __device__ __forceinline__ void st_spinor(void* __restrict__ base, float* __rest
                 else
                     w[q] = f2b(v[8 * b + 2 * q]) | (f2b(v[8 * b + 2 * q + 1]) << 16);
             }
-            p[b * N + n] = make_uint4(w[0], w[1], w[2], w[3]);
+            at_mut<uint4>(base, b * bb, off) = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
 }
 
+// Raw 16-bit spinor load: the stored values without the FP16 site norm
+// (returned separately, 1 for BF16), so that the norm can be applied after
+// the spin projection on 12 instead of 24 numbers.
+template <int P>
+__device__ __forceinline__ float ld_spinor_raw(const void* __restrict__ base, const float* __restrict__ nrm,
+                                               size_t N, size_t n, float (&v)[24]) {
+    static_assert(P == P16 || P == PB16, "16-bit storage only");
+    const uint32_t off = (uint32_t)n * 16u;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const uint4 t = at<uint4>(base, b * N * 16, off);
+        uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (P == P16) {
+                v[8 * b + 2 * q] = h2f(w[q] & 0xffffu);
+                v[8 * b + 2 * q + 1] = h2f(w[q] >> 16);
+            } else {
+                v[8 * b + 2 * q] = b2f(w[q] & 0xffffu);
+                v[8 * b + 2 * q + 1] = b2f(w[q] >> 16);
+            }
+        }
+    }
+    if constexpr (P == P16) return nrm[n];
+    return 1.0f;
+}
+
 // ---------------------------------------------------------------------------
-// links: complex k (row-major 3x3) of direction d at output site
+// links: complex k (row-major 3x3) of direction d at output site.  FP64
+// fields use FP64 links; every lower precision uses FP32 links (their
+// bytes are shared by the Ls slices of a 4D site, so FP32 costs little
+// traffic and saves the 16-bit conversions).
 // ---------------------------------------------------------------------------
+constexpr int link_prec(int p) { return p == P64 ? P64 : P32; }
+
 template <int P>
 __device__ __forceinline__ void ld_link(const void* __restrict__ g, int d, int site, int Vh,
                                         typename PT<P>::A (&u)[18]) {
-    const size_t off = (size_t)d * 9 * Vh + site;
     if constexpr (P == P64) {
-        const double2* p = (const double2*)g;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) { double2 t = p[off + (size_t)k * Vh]; u[2 * k] = t.x; u[2 * k + 1] = t.y; }
-    } else if constexpr (P == P32) {
-        const float2* p = (const float2*)g;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) { float2 t = p[off + (size_t)k * Vh]; u[2 * k] = t.x; u[2 * k + 1] = t.y; }
-    } else {
-        const uint32_t* p = (const uint32_t*)g;
+        const size_t bb = (size_t)Vh * 16;
+        const uint32_t off = (uint32_t)site * 16u;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            uint32_t t = p[off + (size_t)k * Vh];
-            if constexpr (P == P16) { u[2 * k] = h2f(t & 0xffffu); u[2 * k + 1] = h2f(t >> 16); }
-            else { u[2 * k] = b2f(t & 0xffffu); u[2 * k + 1] = b2f(t >> 16); }
+            const double2 t = at<double2>(g, (size_t)(d * 9 + k) * bb, off);
+            u[2 * k] = t.x; u[2 * k + 1] = t.y;
+        }
+    } else {
+        const size_t bb = (size_t)Vh * 8;
+        const uint32_t off = (uint32_t)site * 8u;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float2 t = at<float2>(g, (size_t)(d * 9 + k) * bb, off);
+            u[2 * k] = t.x; u[2 * k + 1] = t.y;
         }
     }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumber them so that XCD x works on one contiguous range of
+// logical blocks (neighbouring 4D sites then share an L2).
+__device__ __forceinline__ int xcd_block(int nblk) {
+    constexpr int NX = 8;
+    const int b = blockIdx.x;
+    const int per = nblk / NX, rem = nblk % NX;
+    const int x = b % NX, q = b / NX;
+    return x * per + (x < rem ? x : rem) + q;
 }
 
 // ---------------------------------------------------------------------------
@@ -181,6 +238,7 @@ struct HopArgs {
     const void* aux2; const float* aux2_nrm;
     const void* gauge;   // links of the output parity, [8][9][Vh]
     const int* nbr;      // neighbour cb index of the output parity, [8][Vh]
+    const int* order;    // traversal order: logical block -> block of NS sites (nullable)
     int Vh, Ls, NS;
     size_t N;
     double mp, mm;
