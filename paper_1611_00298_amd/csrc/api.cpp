@@ -43,6 +43,7 @@ hipError_t launch_zero(int prec, void* f, float* fn, size_t n5, size_t N, int nb
 hipError_t launch_ingest_gauge(const void* U, void* G, int* nbr, const int L[4], int Ls, int aperiodic,
                                hipStream_t st);
 hipError_t launch_gauge_convert(int po, const void* in, void* out, size_t n, hipStream_t st);
+hipError_t launch_gauge_frag(const void* in, void* out, int Vh, hipStream_t st);
 hipError_t launch_nat5_to_dev(const void* nat, void* de, void* dodd, const int L[4], int Ls, size_t N,
                               hipStream_t st);
 hipError_t launch_dev_to_nat5(void* nat, const void* de, const void* dodd, const int L[4], int Ls,
@@ -111,6 +112,7 @@ struct eofa_ctx {
     int* order[4] = {nullptr, nullptr, nullptr, nullptr};   // block traversal order per precision
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
+    void* frag = nullptr;        // FP16 link rows for the matrix-core FP16 hop (4 | Ls)
     double* om = nullptr;
     std::vector<double> om_h;
     double* partial = nullptr;
@@ -126,6 +128,8 @@ struct eofa_ctx {
     long t_count[C_NCLS] = {0};
     double t_ms[C_NCLS] = {0}, t_bytes[C_NCLS] = {0};
     double flops = 0;
+    bool use_mfma = true;
+    int mfma_depth = 3;
 };
 
 namespace {
@@ -223,6 +227,12 @@ struct HopCall {
 };
 
 void run_hop(eofa_ctx* c, const HopCall& h) {
+    // epilogue forms the kernel implements: C(ch A(hop) + cr aux2) + ca B(aux) requires
+    // C = 1 whenever aux is given, and aux2 only with A = 1 unless C = 1
+    if (h.hop && h.aux && h.C.kind != 0) fail(EOFA_EDEVICE, "internal: aux with a non-trivial C");
+    if (h.hop && h.aux2 && h.A.kind != 0 && h.C.kind != 0) fail(EOFA_EDEVICE, "internal: aux2 with A and C");
+    if (!h.hop && h.aux2 && h.C.kind != 0) fail(EOFA_EDEVICE, "internal: aux2 after C");
+    if (!h.hop && !h.aux) fail(EOFA_EDEVICE, "internal: local op without input");
     HopArgs a;
     memset(&a, 0, sizeof(a));
     a.in = h.in ? h.in->d : nullptr;
@@ -237,6 +247,14 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
     a.nbr = c->nbr + (size_t)h.par * 8 * c->Vh;
     a.order = c->order[h.prec];
+    if (h.prec == P16 && c->Ls % 4 == 0 && c->use_mfma) {
+        if (!c->frag) {
+            hipchk(hipMalloc(&c->frag, (size_t)2 * 8 * c->Vh * 96), "hipMalloc(link rows)");
+            hipchk(launch_gauge_frag(c->gauge[P64], c->frag, c->Vh, c->st), "link rows");
+        }
+        a.frag = (const char*)c->frag + (size_t)h.par * 8 * c->Vh * 96;
+        a.depth = c->mfma_depth;
+    }
     a.Vh = c->Vh;
     a.Ls = c->Ls;
     a.NS = c->NS;
@@ -615,6 +633,7 @@ void free_ctx(eofa_ctx* c) {
     for (int p = 0; p < 4; ++p) if (c->order[p]) hipFree(c->order[p]);
     if (c->nbr) hipFree(c->nbr);
     if (c->U_nat) hipFree(c->U_nat);
+    if (c->frag) hipFree(c->frag);
     if (c->om) hipFree(c->om);
     if (c->partial) hipFree(c->partial);
     if (c->sc) hipFree(c->sc);
@@ -654,6 +673,7 @@ void load_gauge(eofa_ctx* c, const void* U) {
     const size_t nc = (size_t)2 * 8 * 9 * c->Vh;
     for (int p = 1; p < 4; ++p)
         if (c->gauge[p]) hipchk(launch_gauge_convert(p, c->gauge[P64], c->gauge[p], nc, c->st), "gauge convert");
+    if (c->frag) hipchk(launch_gauge_frag(c->gauge[P64], c->frag, c->Vh, c->st), "link rows");
 }
 
 }  // namespace
@@ -714,7 +734,7 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             hipchk(hipMalloc(&c->gauge[P64], (size_t)2 * 8 * 9 * c->Vh * 16), "hipMalloc(gauge)");
             hipchk(hipMalloc(&c->U_nat, (size_t)4 * c->V * 9 * 16), "hipMalloc(U)");
             {
-                const int bz_default[4] = {0, 0, 0, 0};   // measured: no gain at 24^3x64, Ls=24
+                const int bz_default[4] = {0, 2, 2, 2};   // measured best at 24^3x64, Ls=24
                 for (int p = 0; p < 4; ++p) {
                     int bz = bz_default[p];
                     if (const char* e = getenv("EOFA_ZBLOCK")) bz = atoi(e);
@@ -724,6 +744,8 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
                            "copy order");
                 }
             }
+            if (const char* e = getenv("EOFA_NO_MFMA")) c->use_mfma = atoi(e) == 0;
+            if (const char* e = getenv("EOFA_MFMA_DEPTH")) c->mfma_depth = atoi(e);
             c->om_h.resize(c->Ls);
             for (int s = 0; s < c->Ls; ++s) c->om_h[s] = std::pow(-c->c5 / c->b5, s);
             hipchk(hipMalloc((void**)&c->om, sizeof(double) * c->Ls), "hipMalloc(omega)");

@@ -103,62 +103,270 @@ __device__ __forceinline__ void su3_mul(const A (&U)[18], const A (&h)[12], A (&
         }
 }
 
+// One direction's operands, loaded one direction ahead of their use.
+template <int P> struct Stage {
+    using A = typename PT<P>::A;
+    A psi[24];    // neighbour spinor (16-bit fields: raw values, scale in nrm)
+    A U[18];      // link
+    float nrm;
+};
+
+template <int P, int D>
+__device__ __forceinline__ void load_stage(const HopArgs& a, int site, int s, int nb, Stage<P>& st) {
+    const size_t n = (size_t)nb * a.Ls + s;
+    if constexpr (P == P16 || P == PB16) st.nrm = ld_spinor_raw<P>(a.in, a.in_nrm, a.N, n, st.psi);
+    else ld_spinor<P>(a.in, a.in_nrm, a.N, n, st.psi);
+    ld_link<P>(a.gauge, D, site, a.Vh, st.U);
+}
+
 template <int P, bool DAG, int D>
-__device__ __forceinline__ void hop_dir(const HopArgs& a, int site, int s,
-                                        typename PT<P>::A (&acc)[24]) {
+__device__ __forceinline__ void compute_stage(const Stage<P>& st, typename PT<P>::A (&acc)[24]) {
     using A = typename PT<P>::A;
     constexpr int MU = D & 3;
     constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
-    const int nb = a.nbr[(size_t)D * a.Vh + site];
-    A psi[24];
     A h[12];
-    if constexpr (P == P16 || P == PB16) {
-        const float sc = ld_spinor_raw<P>(a.in, a.in_nrm, a.N, (size_t)nb * a.Ls + s, psi);
-        project<MU, SG>(psi, h);
-        if constexpr (P == P16) {
+    project<MU, SG>(st.psi, h);
+    if constexpr (P == P16) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) h[k] *= sc;
-        }
-    } else {
-        ld_spinor<P>(a.in, a.in_nrm, a.N, (size_t)nb * a.Ls + s, psi);
-        project<MU, SG>(psi, h);
+        for (int k = 0; k < 12; ++k) h[k] *= st.nrm;
     }
-    A U[18];
-    ld_link<P>(a.gauge, D, site, a.Vh, U);
     A u[12];
-    su3_mul(U, h, u);
+    su3_mul(st.U, h, u);
     reconstruct<MU, SG>(u, acc);
 }
 
-// ---------------------------------------------------------------------------
-// 5D-local operators through LDS.  lds is [24][NT]; lane tid = sl*Ls + s.
-// Shift S = L: upper spins (P+) shift down (s-1, wrap -m+), lower spins
-// (P-) shift up (s+1, wrap -m-).  S = L^T: the directions swap.
-// ---------------------------------------------------------------------------
-template <typename A>
-__device__ __forceinline__ void lds_put(A* lds, int NT, int tid, const A (&v)[24]) {
+// all eight directions, operands of direction d+1 in flight while d computes
+template <int P, bool DAG>
+__device__ __forceinline__ void hop_all(const HopArgs& a, int site, int s, typename PT<P>::A (&acc)[24]) {
+    int nb[8];
 #pragma unroll
-    for (int k = 0; k < 24; ++k) lds[k * NT + tid] = v[k];
+    for (int d = 0; d < 8; ++d) nb[d] = a.nbr[(size_t)d * a.Vh + site];
+    if constexpr (P == P64) {   // registers allow one stage in flight
+        Stage<P> st;
+        load_stage<P, 0>(a, site, s, nb[0], st); compute_stage<P, DAG, 0>(st, acc);
+        load_stage<P, 1>(a, site, s, nb[1], st); compute_stage<P, DAG, 1>(st, acc);
+        load_stage<P, 2>(a, site, s, nb[2], st); compute_stage<P, DAG, 2>(st, acc);
+        load_stage<P, 3>(a, site, s, nb[3], st); compute_stage<P, DAG, 3>(st, acc);
+        load_stage<P, 4>(a, site, s, nb[4], st); compute_stage<P, DAG, 4>(st, acc);
+        load_stage<P, 5>(a, site, s, nb[5], st); compute_stage<P, DAG, 5>(st, acc);
+        load_stage<P, 6>(a, site, s, nb[6], st); compute_stage<P, DAG, 6>(st, acc);
+        load_stage<P, 7>(a, site, s, nb[7], st); compute_stage<P, DAG, 7>(st, acc);
+        return;
+    }
+    Stage<P> s0, s1;
+    load_stage<P, 0>(a, site, s, nb[0], s0);
+    load_stage<P, 1>(a, site, s, nb[1], s1);
+    compute_stage<P, DAG, 0>(s0, acc);
+    load_stage<P, 2>(a, site, s, nb[2], s0);
+    compute_stage<P, DAG, 1>(s1, acc);
+    load_stage<P, 3>(a, site, s, nb[3], s1);
+    compute_stage<P, DAG, 2>(s0, acc);
+    load_stage<P, 4>(a, site, s, nb[4], s0);
+    compute_stage<P, DAG, 3>(s1, acc);
+    load_stage<P, 5>(a, site, s, nb[5], s1);
+    compute_stage<P, DAG, 4>(s0, acc);
+    load_stage<P, 6>(a, site, s, nb[6], s0);
+    compute_stage<P, DAG, 5>(s1, acc);
+    load_stage<P, 7>(a, site, s, nb[7], s1);
+    compute_stage<P, DAG, 6>(s0, acc);
+    compute_stage<P, DAG, 7>(s1, acc);
 }
 
+// ---------------------------------------------------------------------------
+// FP16 hop on the matrix cores.  For 4 | Ls the four lanes of every 4x4x4
+// MFMA block (v_mfma_f32_4x4x4_16b_f16: 16 independent blocks per wave,
+// lane 4b+j supplies column j of B and row j of A) belong to one 4D site, so
+// the link is the shared A operand and each lane's projected half spinor is
+// its own B column:  (U h)_real = Ureal . h_real with
+//   Ureal rows (re0, im0, re1, im1, re2, im2), columns in the same order,
+//   row re_a = [Ur_a0, -Ui_a0, Ur_a1, -Ui_a1, Ur_a2, -Ui_a2, 0, 0]
+//   row im_a = [Ui_a0,  Ur_a0, Ui_a1,  Ur_a1, Ui_a2,  Ur_a2, 0, 0].
+// Inputs are FP16 (the stored spinor and an FP16 copy of the link), the
+// products accumulate in FP32.  The spin projection is one packed FP16 add
+// per complex number; the site norm and the reconstruction are FP32 FMAs.
+// ---------------------------------------------------------------------------
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ h2v as_h2(uint32_t w) { return __builtin_bit_cast(h2v, w); }
+__device__ __forceinline__ h2v mul_i(h2v y) {   // i y
+    h2v t = __builtin_shufflevector(y, y, 1, 0);
+    t.x = -t.x;
+    return t;
+}
+__device__ __forceinline__ h4v cat(h2v a, h2v b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3); }
+__device__ __forceinline__ h4v h4_of(uint32_t a, uint32_t b) { return cat(as_h2(a), as_h2(b)); }
+
+// h_j (j = 0, 1) for colours c = 0..2 from the raw words w[3k + c]
+template <int MU, int SG>
+__device__ __forceinline__ void project_h2(const uint32_t (&w)[12], h2v (&h)[6]) {
+    const _Float16 sg = (_Float16)SG;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const h2v p0 = as_h2(w[c]), p1 = as_h2(w[3 + c]), p2 = as_h2(w[6 + c]), p3 = as_h2(w[9 + c]);
+        if constexpr (MU == 0) {        // h0 = p0 - sg i p3, h1 = p1 - sg i p2
+            h[c] = p0 - sg * mul_i(p3);  h[3 + c] = p1 - sg * mul_i(p2);
+        } else if constexpr (MU == 1) { // h0 = p0 - sg p3,   h1 = p1 + sg p2
+            h[c] = p0 - sg * p3;         h[3 + c] = p1 + sg * p2;
+        } else if constexpr (MU == 2) { // h0 = p0 - sg i p2, h1 = p1 + sg i p3
+            h[c] = p0 - sg * mul_i(p2);  h[3 + c] = p1 + sg * mul_i(p3);
+        } else {                        // h0 = p0 + sg p2,   h1 = p1 + sg p3
+            h[c] = p0 + sg * p2;         h[3 + c] = p1 + sg * p3;
+        }
+    }
+}
+
+// acc_up += f u ; acc_lo += f sg A^dag u  (FMAs)
+template <int MU, int SG>
+__device__ __forceinline__ void reconstruct_f(const float (&u)[12], float f, float (&acc)[24]) {
+    const float g = SG * f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float r0 = u[2 * c], i0 = u[2 * c + 1];
+        const float r1 = u[6 + 2 * c], i1 = u[6 + 2 * c + 1];
+        acc[2 * c] = fmadd(f, r0, acc[2 * c]);
+        acc[2 * c + 1] = fmadd(f, i0, acc[2 * c + 1]);
+        acc[2 * (3 + c)] = fmadd(f, r1, acc[2 * (3 + c)]);
+        acc[2 * (3 + c) + 1] = fmadd(f, i1, acc[2 * (3 + c) + 1]);
+        float* l2 = &acc[2 * (6 + c)];
+        float* l3 = &acc[2 * (9 + c)];
+        if constexpr (MU == 0) {
+            l2[0] = fmadd(-g, i1, l2[0]); l2[1] = fmadd(g, r1, l2[1]);
+            l3[0] = fmadd(-g, i0, l3[0]); l3[1] = fmadd(g, r0, l3[1]);
+        } else if constexpr (MU == 1) {
+            l2[0] = fmadd(g, r1, l2[0]);  l2[1] = fmadd(g, i1, l2[1]);
+            l3[0] = fmadd(-g, r0, l3[0]); l3[1] = fmadd(-g, i0, l3[1]);
+        } else if constexpr (MU == 2) {
+            l2[0] = fmadd(-g, i0, l2[0]); l2[1] = fmadd(g, r0, l2[1]);
+            l3[0] = fmadd(g, i1, l3[0]);  l3[1] = fmadd(-g, r1, l3[1]);
+        } else {
+            l2[0] = fmadd(g, r0, l2[0]);  l2[1] = fmadd(g, i0, l2[1]);
+            l3[0] = fmadd(g, r1, l3[0]);  l3[1] = fmadd(g, i1, l3[1]);
+        }
+    }
+}
+
+struct MStage {
+    uint32_t w[12];   // raw FP16 neighbour spinor
+    float nrm;
+    uint4 r0, r1;     // link rows lane4 and 4 + lane4
+};
+
+__device__ __forceinline__ void load_mstage(const HopArgs& a, int D, int site, int s, int lane4, int nb, MStage& st) {
+    const uint32_t n = (uint32_t)nb * a.Ls + s;
+    const uint32_t off = n * 16u;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const uint4 t = at<uint4>(a.in, (size_t)b * a.N * 16, off);
+        st.w[4 * b] = t.x; st.w[4 * b + 1] = t.y; st.w[4 * b + 2] = t.z; st.w[4 * b + 3] = t.w;
+    }
+    st.nrm = a.in_nrm[n];
+    const uint32_t loff = ((uint32_t)D * (uint32_t)a.Vh + (uint32_t)site) * 96u;
+    st.r0 = at<uint4>(a.frag, 0, loff + 16u * lane4);
+    st.r1 = make_uint4(0, 0, 0, 0);
+    if (lane4 < 2) st.r1 = at<uint4>(a.frag, 0, loff + 64u + 16u * lane4);
+}
+
+template <bool DAG, int D>
+__device__ __forceinline__ void compute_mstage(const MStage& st, float (&acc)[24]) {
+    constexpr int MU = D & 3;
+    constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
+    h2v h[6];
+    project_h2<MU, SG>(st.w, h);
+    const h4v A00 = h4_of(st.r0.x, st.r0.y), A01 = h4_of(st.r0.z, st.r0.w);
+    const h4v A10 = h4_of(st.r1.x, st.r1.y), A11 = h4_of(st.r1.z, st.r1.w);
+    const h2v z2 = {(_Float16)0, (_Float16)0};
+    float u[12];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const h4v B0 = cat(h[3 * j], h[3 * j + 1]);
+        const h4v B1 = cat(h[3 * j + 2], z2);
+        f4v c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        c0 = __builtin_amdgcn_mfma_f32_4x4x4f16(A00, B0, c0, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f32_4x4x4f16(A01, B1, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_4x4x4f16(A10, B0, c1, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_4x4x4f16(A11, B1, c1, 0, 0, 0);
+        u[6 * j + 0] = c0[0]; u[6 * j + 1] = c0[1]; u[6 * j + 2] = c0[2]; u[6 * j + 3] = c0[3];
+        u[6 * j + 4] = c1[0]; u[6 * j + 5] = c1[1];
+    }
+    reconstruct_f<MU, SG>(u, st.nrm, acc);
+}
+
+template <bool DAG>
+__device__ __forceinline__ void compute_mstage_rt(const MStage& st, int d, float (&acc)[24]) {
+    switch (d) {   // d is a compile-time constant after unrolling
+    case 0: compute_mstage<DAG, 0>(st, acc); break;
+    case 1: compute_mstage<DAG, 1>(st, acc); break;
+    case 2: compute_mstage<DAG, 2>(st, acc); break;
+    case 3: compute_mstage<DAG, 3>(st, acc); break;
+    case 4: compute_mstage<DAG, 4>(st, acc); break;
+    case 5: compute_mstage<DAG, 5>(st, acc); break;
+    case 6: compute_mstage<DAG, 6>(st, acc); break;
+    default: compute_mstage<DAG, 7>(st, acc); break;
+    }
+}
+
+// eight directions with DEPTH directions' operands in flight
+template <bool DAG, int DEPTH>
+__device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int site, int s, int lane4, float (&acc)[24]) {
+    int nb[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) nb[d] = a.nbr[(size_t)d * a.Vh + site];
+    MStage st[DEPTH];
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) load_mstage(a, d, site, s, lane4, nb[d], st[d]);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        compute_mstage_rt<DAG>(st[d % DEPTH], d, acc);
+        if (d + DEPTH < 8) load_mstage(a, d + DEPTH, site, s, lane4, nb[d + DEPTH], st[d % DEPTH]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 5D-local operators through LDS.  The tile holds one row of 24 reals per
+// work-item (row tid = sl*Ls + s, odd stride STR so that column sweeps are
+// free of bank conflicts).  A shift S = L moves the upper spins (P+) down
+// (s-1, wrap -m+) and the lower spins (P-) up (s+1, wrap -m-); S = L^T
+// swaps the directions.
+//   row exchange : each work-item reads the shifted neighbour row (a + b S)
+//   column sweep : work-item (sl, s) walks component c = s (+Ls, ...) of its
+//                  site along the fifth dimension; bidiagonal ops take one
+//                  pass and (a + b S)^-1 two: the recursion
+//                  z_q = x_q / a + w z_{q-1} (w = -b/a, q the position along
+//                  the shift) and the rank-one wrap-around correction
+//                  y_q = z_q - m w^(q+1) z_last / (1 + m w^Ls).
+// ---------------------------------------------------------------------------
+constexpr int STR = 25;
+
 template <typename A>
-__device__ void op_bidiag_lds(A* lds, int NT, int tid, int s, int Ls, A (&v)[24],
-                              const Op5& op, A mp, A mm) {
-    lds_put(lds, NT, tid, v);
-    __syncthreads();
+__device__ __forceinline__ void put_row(A* T, int tid, const A (&v)[24]) {
+    A* r = T + tid * STR;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) r[k] = v[k];
+}
+template <typename A>
+__device__ __forceinline__ void get_row(const A* T, int tid, A (&v)[24]) {
+    const A* r = T + tid * STR;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = r[k];
+}
+
+// out = a x + b S x for the row x staged in T (all rows staged, synced)
+template <typename A>
+__device__ __forceinline__ void row_bidiag(const A* T, int tid, int s, int Ls, const A (&x)[24],
+                                           A (&out)[24], A a, A b, int tr, A mp, A mm) {
     const int tdn = (s == 0) ? tid + Ls - 1 : tid - 1;
     const int tup = (s == Ls - 1) ? tid - (Ls - 1) : tid + 1;
-    const bool up_down = !op.tr;   // upper chirality shifts down for L
-    const int tu = up_down ? tdn : tup;
-    const int tl = up_down ? tup : tdn;
-    const A fu = (up_down ? s == 0 : s == Ls - 1) ? -mp : A(1);
-    const A fl = (up_down ? s == Ls - 1 : s == 0) ? -mm : A(1);
-    const A ca = (A)op.a, cb = (A)op.b;
+    const bool up_down = !tr;
+    const A* ru = T + (up_down ? tdn : tup) * STR;
+    const A* rl = T + (up_down ? tup : tdn) * STR;
+    const A fu = b * ((up_down ? s == 0 : s == Ls - 1) ? -mp : A(1));
+    const A fl = b * ((up_down ? s == Ls - 1 : s == 0) ? -mm : A(1));
 #pragma unroll
-    for (int k = 0; k < 12; ++k) v[k] = ca * v[k] + cb * fu * lds[k * NT + tu];
+    for (int k = 0; k < 12; ++k) out[k] = fmadd(fu, ru[k], a * x[k]);
 #pragma unroll
-    for (int k = 12; k < 24; ++k) v[k] = ca * v[k] + cb * fl * lds[k * NT + tl];
-    __syncthreads();
+    for (int k = 12; k < 24; ++k) out[k] = fmadd(fl, rl[k], a * x[k]);
 }
 
 template <typename A>
@@ -168,59 +376,63 @@ __device__ __forceinline__ A ipow(A x, int e) {
     return r;
 }
 
-// v <- (a + b S)^-1 v.  Along the shift direction (position q = s for a
-// down shift, q = Ls-1-s for an up shift) the solution is
-//   z_q = (1/a) sum_{j<=q} w^j v_{q-j},  w = -b/a   (scan)
-//   y_q = z_q - m w^(q+1) z_last / (1 + m w^Ls)    (wrap-around term)
+// in-place column ops; element at position q along the shift is col[sq(q)*STR]
 template <typename A>
-__device__ void op_inverse_lds(A* lds, int NT, int tid, int s, int Ls, A (&v)[24],
-                               const Op5& op, A mp, A mm) {
-    const A ia = A(1) / (A)op.a;
-    const A w = -(A)op.b * ia;
-    const bool up_down = !op.tr;
-    const int qu = up_down ? s : Ls - 1 - s;
-    const int ql = up_down ? Ls - 1 - s : s;
-    const int du = up_down ? -1 : 1;   // partner offset direction for upper comps
-    const int dl = -du;
-#pragma unroll
-    for (int k = 0; k < 24; ++k) v[k] *= ia;
-    A wd = w;
-    for (int d = 1; d < Ls; d <<= 1) {
-        lds_put(lds, NT, tid, v);
-        __syncthreads();
-        if (qu >= d) {
-            const int t = tid + du * d;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) v[k] += wd * lds[k * NT + t];
-        }
-        if (ql >= d) {
-            const int t = tid + dl * d;
-#pragma unroll
-            for (int k = 12; k < 24; ++k) v[k] += wd * lds[k * NT + t];
-        }
-        __syncthreads();
-        wd *= wd;
+__device__ void col_bidiag(A* col, int Ls, bool down, A a, A b, A m) {
+    const int s0 = down ? 0 : Ls - 1, ds = down ? 1 : -1;
+    A prev = -m * col[(s0 + ds * (Ls - 1)) * STR];
+    int sidx = s0;
+    for (int q = 0; q < Ls; ++q, sidx += ds) {
+        const A x = col[sidx * STR];
+        col[sidx * STR] = fmadd(b, prev, a * x);
+        prev = x;
     }
-    lds_put(lds, NT, tid, v);
-    __syncthreads();
-    const int base = tid - s;
-    const int lu = up_down ? base + Ls - 1 : base;
-    const int ll = up_down ? base : base + Ls - 1;
-    const A wL = ipow(w, Ls);
-    const A cu = -mp * ipow(w, qu + 1) / (A(1) + mp * wL);
-    const A cl = -mm * ipow(w, ql + 1) / (A(1) + mm * wL);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) v[k] += cu * lds[k * NT + lu];
-#pragma unroll
-    for (int k = 12; k < 24; ++k) v[k] += cl * lds[k * NT + ll];
-    __syncthreads();
 }
 
 template <typename A>
-__device__ __forceinline__ void apply_op_lds(A* lds, int NT, int tid, int s, int Ls, A (&v)[24],
-                                             const Op5& op, A mp, A mm) {
-    if (op.kind == 1) op_bidiag_lds(lds, NT, tid, s, Ls, v, op, mp, mm);
-    else if (op.kind == 2) op_inverse_lds(lds, NT, tid, s, Ls, v, op, mp, mm);
+__device__ void col_inverse(A* col, int Ls, bool down, A a, A b, A m) {
+    const int s0 = down ? 0 : Ls - 1, ds = down ? 1 : -1;
+    const A ia = A(1) / a, w = -b * ia;
+    A z = 0;
+    int sidx = s0;
+    for (int q = 0; q < Ls; ++q, sidx += ds) {
+        z = fmadd(w, z, ia * col[sidx * STR]);
+        col[sidx * STR] = z;
+    }
+    const A K = -m * z / (A(1) + m * ipow(w, Ls));
+    A pw = w;
+    sidx = s0;
+    for (int q = 0; q < Ls; ++q, sidx += ds) {
+        col[sidx * STR] = fmadd(K, pw, col[sidx * STR]);
+        pw *= w;
+    }
+}
+
+template <typename A>
+__device__ __forceinline__ void col_op(A* col, int Ls, bool upper, const Op5& op, A mp, A mm) {
+    const bool down = upper != (op.tr != 0);
+    const A m = upper ? mp : mm;
+    if (op.kind == 1) col_bidiag(col, Ls, down, (A)op.a, (A)op.b, m);
+    else if (op.kind == 2) col_inverse(col, Ls, down, (A)op.a, (A)op.b, m);
+}
+
+// v <- op2(scale * op1(v)) through a column sweep of the staged tile
+template <typename A>
+__device__ void column_phase(A* T, int tid, int sl, int s, int Ls, A (&v)[24], const Op5& op1,
+                             A scale, const Op5& op2, A mp, A mm) {
+    put_row(T, tid, v);
+    __syncthreads();
+    for (int c = s; c < 24; c += Ls) {
+        A* col = T + sl * Ls * STR + c;
+        const bool upper = c < 12;
+        col_op(col, Ls, upper, op1, mp, mm);
+        if (scale != A(1))
+            for (int q = 0; q < Ls; ++q) col[q * STR] *= scale;
+        col_op(col, Ls, upper, op2, mp, mm);
+    }
+    __syncthreads();
+    get_row(T, tid, v);
+    __syncthreads();
 }
 
 // double-precision workgroup sum; result valid in thread 0
@@ -238,8 +450,8 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
     return t;
 }
 
-template <int P, bool DAG, bool HOP>
-__global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
+template <int P, bool DAG, bool HOP, int MF>
+__global__ void __launch_bounds__(256, MF == 8 ? 2 : 3) k_hop(const HopArgs a) {
     using A = typename PT<P>::A;
     extern __shared__ unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
@@ -259,52 +471,86 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = 0;
     if (HOP) {
-        if (active) {
-            hop_dir<P, DAG, 0>(a, site, s, v);
-            hop_dir<P, DAG, 1>(a, site, s, v);
-            hop_dir<P, DAG, 2>(a, site, s, v);
-            hop_dir<P, DAG, 3>(a, site, s, v);
-            hop_dir<P, DAG, 4>(a, site, s, v);
-            hop_dir<P, DAG, 5>(a, site, s, v);
-            hop_dir<P, DAG, 6>(a, site, s, v);
-            hop_dir<P, DAG, 7>(a, site, s, v);
+        if constexpr (MF) {
+            // matrix-core path: every lane takes part (the MFMA needs the
+            // whole wave); inactive lanes read site 0 and discard it
+            hop_all_mfma<DAG, MF>(a, active ? site : 0, s, tid & 3, v);
+            if (!active) {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] = 0;
+            }
+        } else if (active) {
+            hop_all<P, DAG>(a, site, s, v);
         }
-        apply_op_lds(lds, NT, tid, s, Ls, v, a.opA, mp, mm);
-        const A ch = (A)a.ch;
-#pragma unroll
-        for (int k = 0; k < 24; ++k) v[k] *= ch;
     }
-    if (a.aux && active) {
-        A x[24];
-        ld_spinor<P>(a.aux, a.aux_nrm, a.N, n, x);
-        const A ca = (A)a.ca;
-        if (a.opB.kind == 1) {
-            const bool up_down = !a.opB.tr;
-            const size_t ndn = (s == 0) ? n + Ls - 1 : n - 1;
-            const size_t nup = (s == Ls - 1) ? n - (Ls - 1) : n + 1;
-            A xu[24], xl[24];
-            ld_spinor<P>(a.aux, a.aux_nrm, a.N, up_down ? ndn : nup, xu);
-            ld_spinor<P>(a.aux, a.aux_nrm, a.N, up_down ? nup : ndn, xl);
-            const A fu = (up_down ? s == 0 : s == Ls - 1) ? -mp : A(1);
-            const A fl = (up_down ? s == Ls - 1 : s == 0) ? -mm : A(1);
-            const A ba = (A)a.opB.a, bb = (A)a.opB.b;
+    if (HOP) {
+        A ch = (A)a.ch;
+        bool aux2_done = false;
+        if (a.aux2 && a.opA.kind == 0) {   // fold cr * aux2 in before the 5D ops (A = 1)
+            A x[24];
+            if (active) ld_spinor<P>(a.aux2, a.aux2_nrm, a.N, n, x);
+            else {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) v[k] += ca * (ba * x[k] + bb * fu * xu[k]);
+                for (int k = 0; k < 24; ++k) x[k] = 0;
+            }
+            const A cr = (A)a.cr;
 #pragma unroll
-            for (int k = 12; k < 24; ++k) v[k] += ca * (ba * x[k] + bb * fl * xl[k]);
+            for (int k = 0; k < 24; ++k) v[k] = fmadd(ch, v[k], cr * x[k]);
+            ch = A(1);
+            aux2_done = true;
+        }
+        if (a.opA.kind != 0 || a.opC.kind != 0) {
+            column_phase(lds, tid, sl, s, Ls, v, a.opA, ch, a.opC, mp, mm);
+        } else if (ch != A(1)) {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] *= ch;
+        }
+        if (a.aux) {
+            A x[24];
+            if (active) ld_spinor<P>(a.aux, a.aux_nrm, a.N, n, x);
+            else {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) x[k] = 0;
+            }
+            const A ca = (A)a.ca;
+            if (a.opB.kind == 1) {
+                put_row(lds, tid, x);
+                __syncthreads();
+                A bx[24];
+                row_bidiag(lds, tid, s, Ls, x, bx, (A)a.opB.a, (A)a.opB.b, a.opB.tr, mp, mm);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] = fmadd(ca, bx[k], v[k]);
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] = fmadd(ca, x[k], v[k]);
+            }
+        }
+        if (a.aux2 && !aux2_done && active) {
+            A x[24];
+            ld_spinor<P>(a.aux2, a.aux2_nrm, a.N, n, x);
+            const A cr = (A)a.cr;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] = fmadd(cr, x[k], v[k]);
+        }
+    } else {
+        // local 5D operator: out = C(ca * B(aux)) + cr * aux2
+        if (active) ld_spinor<P>(a.aux, a.aux_nrm, a.N, n, v);
+        if (a.opB.kind != 0 || a.opC.kind != 0) {
+            column_phase(lds, tid, sl, s, Ls, v, a.opB, (A)a.ca, a.opC, mp, mm);
         } else {
+            const A ca = (A)a.ca;
 #pragma unroll
-            for (int k = 0; k < 24; ++k) v[k] += ca * x[k];
+            for (int k = 0; k < 24; ++k) v[k] *= ca;
+        }
+        if (a.aux2 && active) {
+            A x[24];
+            ld_spinor<P>(a.aux2, a.aux2_nrm, a.N, n, x);
+            const A cr = (A)a.cr;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] = fmadd(cr, x[k], v[k]);
         }
     }
-    if (a.aux2 && active) {
-        A x[24];
-        ld_spinor<P>(a.aux2, a.aux2_nrm, a.N, n, x);
-        const A cr = (A)a.cr;
-#pragma unroll
-        for (int k = 0; k < 24; ++k) v[k] += cr * x[k];
-    }
-    apply_op_lds(lds, NT, tid, s, Ls, v, a.opC, mp, mm);
     if (active) st_spinor<P>(a.out, a.out_nrm, a.N, n, v);
     if (a.partial) {
         double x = 0;
@@ -352,9 +598,11 @@ __global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_n
         }
         st_spinor<P>(p, p_nrm, N, n, v);
     }
-    Op5 op{1, 0, b5, c5};
-    op_bidiag_lds(lds, NT, tid, s, Ls, v, op, (A)mp_, (A)mm_);
-    if (active) st_spinor<P>(pt, pt_nrm, N, n, v);
+    put_row(lds, tid, v);
+    __syncthreads();
+    A t[24];
+    row_bidiag(lds, tid, s, Ls, v, t, (A)b5, (A)c5, 0, (A)mp_, (A)mm_);
+    if (active) st_spinor<P>(pt, pt_nrm, N, n, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -364,9 +612,18 @@ template <int P, bool DAG, bool HOP>
 static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     using A = typename PT<P>::A;
     const int NT = a.NS * a.Ls;
-    const bool need_lds = (HOP && a.opA.kind != 0) || a.opC.kind != 0;
-    const size_t shm = need_lds ? (size_t)24 * NT * sizeof(A) : 0;
-    hipLaunchKernelGGL((k_hop<P, DAG, HOP>), dim3(nblk), dim3(NT), shm, st, a);
+    const bool need_lds = HOP ? (a.opA.kind != 0 || a.opC.kind != 0 || (a.aux && a.opB.kind != 0))
+                              : (a.opB.kind != 0 || a.opC.kind != 0);
+    const size_t shm = need_lds ? (size_t)STR * NT * sizeof(A) : 0;
+    if constexpr (P == P16 && HOP) {
+        if (a.frag) {
+            if (a.depth >= 8) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 8>), dim3(nblk), dim3(NT), shm, st, a);
+            else if (a.depth == 3) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 3>), dim3(nblk), dim3(NT), shm, st, a);
+            else hipLaunchKernelGGL((k_hop<P, DAG, HOP, 2>), dim3(nblk), dim3(NT), shm, st, a);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_hop<P, DAG, HOP, 0>), dim3(nblk), dim3(NT), shm, st, a);
     return hipGetLastError();
 }
 
@@ -394,7 +651,7 @@ hipError_t launch_pupdate(int prec, const void* z, const float* zn, void* p, flo
     switch (prec) {
 #define EOFA_CASE(PP)                                                                         \
     case PP: {                                                                                \
-        const size_t shm = (size_t)24 * NT * sizeof(typename PT<PP>::A);                      \
+        const size_t shm = (size_t)STR * NT * sizeof(typename PT<PP>::A);                     \
         hipLaunchKernelGGL((k_pupdate<PP>), dim3(nblk), dim3(NT), shm, st, z, zn, p, pn, pt,  \
                            ptn, sc, i_new, i_old, first, Vh, Ls, NS, N, b5, c5, mp, mm);      \
         return hipGetLastError();                                                             \

@@ -239,6 +239,8 @@ struct HopArgs {
     const void* gauge;   // links of the output parity, [8][9][Vh]
     const int* nbr;      // neighbour cb index of the output parity, [8][Vh]
     const int* order;    // traversal order: logical block -> block of NS sites (nullable)
+    const void* frag;    // FP16 link rows for the matrix-core path, [8][Vh][6][8] (nullable)
+    int depth;           // directions of operands kept in flight (matrix-core path)
     int Vh, Ls, NS;
     size_t N;
     double mp, mm;
