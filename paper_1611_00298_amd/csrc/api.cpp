@@ -24,15 +24,19 @@
 
 namespace eofa {
 hipError_t launch_hop(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
-hipError_t launch_pupdate(int prec, const void* z, const float* zn, void* p, float* pn, void* pt,
+hipError_t launch_pupdate(int prec, const void* z, const float* zn, const void* po, const float* pon,
+                          void* p, float* pn, void* pt,
                           float* ptn, const double* sc, int i_new, int i_old, int first, int Vh,
                           int Ls, int NS, size_t N, double b5, double c5, double mp, double mm,
                           int nblk, hipStream_t st);
+hipError_t launch_r_update(int prec, void* r, float* rn, const void* w, const float* wn, double* sc,
+                           int i_num, int i_den, int i_save, size_t n5, size_t N, double* partial,
+                           int nblk, hipStream_t st);
+hipError_t launch_x_batch(int prec, void* x, float* xn, const void* const* p, const float* const* pn,
+                          const int* slots, int cnt, const double* sc, size_t n5, size_t N, int nblk,
+                          hipStream_t st);
 int blas_blocks(size_t n5);
 hipError_t launch_reduce(const double* partial, int n, double* out, int slot, hipStream_t st);
-hipError_t launch_xr_update(int prec, void* x, float* xn, const void* p, const float* pn, void* r,
-                            float* rn, const void* w, const float* wn, const double* sc, int i_num,
-                            int i_den, size_t n5, size_t N, double* partial, int nblk, hipStream_t st);
 hipError_t launch_norm2(int prec, const void* f, const float* fn, size_t n5, size_t N,
                         double* partial, int nblk, hipStream_t st);
 hipError_t launch_convert(int pi, int po, const void* in, const float* inn, void* out, float* outn,
@@ -134,7 +138,9 @@ struct eofa_ctx {
 
 namespace {
 
-enum Slot { S_WW = 0, S_ZZ0 = 1, S_ZZ1 = 2, S_RR = 3, S_B2 = 4, S_T0 = 5, S_T1 = 6, S_NSLOT = 16 };
+enum Slot { S_WW = 0, S_ZZ0 = 1, S_ZZ1 = 2, S_RR = 3, S_B2 = 4, S_T0 = 5, S_T1 = 6, S_ALPHA = 8,
+            S_NSLOT = 16 };
+constexpr int XBATCH = 8;   // search directions per batched solution update
 
 size_t half_bytes(const eofa_ctx* c, int prec) { return (size_t)16 * nblocks_of(prec) * c->N; }
 
@@ -404,7 +410,8 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
     const int px = mixed ? P32 : P64;
     Half& r = mixed ? ws(c, "r_lo", prec) : r64;
     Half& z = ws(c, "z", prec);
-    Half& p = ws(c, "p", prec);
+    Half* pr[XBATCH];   // ring of search directions p_k (buffer k mod XBATCH)
+    for (int j = 0; j < XBATCH; ++j) pr[j] = &ws(c, "p" + std::to_string(j), prec);
     Half& pt = ws(c, "pt", prec);
     Half& w = ws(c, "w", prec);
     Half& tmp = ws(c, "tmp_lo_e", prec);
@@ -413,53 +420,84 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
         convert(c, r64, r);
         zero(c, xl);
     }
+    // x += sum alpha_j p_j for the pending directions [pending0, k]
+    int pending0 = 0;
+    auto flush = [&](int k) {
+        const int cnt = k - pending0 + 1;
+        if (cnt <= 0) return;
+        const void* pp[XBATCH];
+        const float* pn[XBATCH];
+        int sl[XBATCH];
+        for (int j = 0; j < cnt; ++j) {
+            const int it = pending0 + j;
+            pp[j] = pr[it % XBATCH]->d;
+            pn[j] = pr[it % XBATCH]->nrm;
+            sl[j] = S_ALPHA + it % XBATCH;
+        }
+        const int ev = timing_begin(c);
+        hipchk(launch_x_batch(prec, xl.d, xl.nrm, pp, pn, sl, cnt, c->sc, c->n5, c->N, c->nblk_blas, c->st),
+               "x update");
+        timing_end(c, ev, C_BLAS, (double)c->n5 * (2.0 * spinor_bytes(px) + cnt * spinor_bytes(prec)));
+        c->flops += 48.0 * cnt * (double)c->n5;
+        pending0 = k + 1;
+    };
     int cur = S_ZZ0, nxt = S_ZZ1;
-    // z = Mhat^dag r ; p = z ; pt = Dtilde p
+    // z = Mhat^dag r ; p_0 = z ; pt = Dtilde p_0
     schur_k3(c, prec, r, tmp, mp, mm);
     schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
     reduce(c, nb, cur);
-    hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pt.d, pt.nrm, c->sc, cur, cur, 1, c->Vh, c->Ls,
-                          c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+    hipchk(launch_pupdate(prec, z.d, z.nrm, nullptr, nullptr, pr[0]->d, pr[0]->nrm, pt.d, pt.nrm, c->sc, cur,
+                          cur, 1, c->Vh, c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
     double rmax = std::sqrt(rr);
+    int k = 0;
     while (res.iters < maxiter) {
+        Half& p = *pr[k % XBATCH];
         // w = Mhat p, |w|^2
         schur_k1(c, prec, pt, tmp, mp, mm);
         schur_k2(c, prec, tmp, p, w, mp, mm, c->partial);
         reduce(c, nb, S_WW);
-        // x += alpha p, r -= alpha w, |r|^2
+        // r -= alpha w, |r|^2 (alpha kept for the batched x update)
         {
             const int ev = timing_begin(c);
-            hipchk(launch_xr_update(prec, xl.d, xl.nrm, p.d, p.nrm, r.d, r.nrm, w.d, w.nrm, c->sc, cur,
-                                    S_WW, c->n5, c->N, c->partial, c->nblk_blas, c->st), "xr_update");
-            timing_end(c, ev, C_BLAS, (double)c->n5 * (2.0 * spinor_bytes(px) + 5.0 * spinor_bytes(prec)));
-            c->flops += 96.0 * (double)c->n5;
+            hipchk(launch_r_update(prec, r.d, r.nrm, w.d, w.nrm, c->sc, cur, S_WW, S_ALPHA + k % XBATCH,
+                                   c->n5, c->N, c->partial, c->nblk_blas, c->st), "r update");
+            timing_end(c, ev, C_BLAS, (double)c->n5 * 3.0 * spinor_bytes(prec));
+            c->flops += 48.0 * (double)c->n5;
         }
         reduce(c, c->nblk_blas, S_RR);
         res.iters++;
         rr = read_slot(c, S_RR);
         check_finite(rr, "residual norm");
         const double rn = std::sqrt(rr);
+        bool stop = false;
         if (mixed && (rn <= delta * rmax || rn <= thresh)) {
-            // reliable update: fold x_lo into x, recompute r in FP64
+            // reliable update: fold the directions into x_lo, x_lo into x, recompute r in FP64
+            flush(k);
             hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
             rr = true_residual();
             check_finite(rr, "true residual");
             res.reliable++;
             rmax = std::sqrt(rr);
-            if (rmax <= thresh) { res.converged = true; break; }
-            convert(c, r64, r);
+            if (rmax <= thresh) { res.converged = true; stop = true; }
+            else convert(c, r64, r);
         } else if (!mixed && rn <= thresh) {
+            flush(k);
             res.converged = true;
-            break;
+            stop = true;
         }
-        // z = Mhat^dag r, |z|^2 ; p = z + beta p
+        if (stop) break;
+        if (k - pending0 + 1 == XBATCH) flush(k);
+        if (res.iters >= maxiter) { flush(k); break; }
+        // z = Mhat^dag r, |z|^2 ; p_{k+1} = z + beta p_k ; pt = Dtilde p_{k+1}
         schur_k3(c, prec, r, tmp, mp, mm);
         schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
         reduce(c, nb, nxt);
-        hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pt.d, pt.nrm, c->sc, nxt, cur, 0, c->Vh,
-                              c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+        Half& pn1 = *pr[(k + 1) % XBATCH];
+        hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pn1.d, pn1.nrm, pt.d, pt.nrm, c->sc, nxt, cur, 0,
+                              c->Vh, c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
         c->flops += 72.0 * (double)c->n5 + 48.0 * (double)c->n5;
         std::swap(cur, nxt);
+        ++k;
     }
     if (mixed && !res.converged)
         hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
@@ -734,7 +772,7 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             hipchk(hipMalloc(&c->gauge[P64], (size_t)2 * 8 * 9 * c->Vh * 16), "hipMalloc(gauge)");
             hipchk(hipMalloc(&c->U_nat, (size_t)4 * c->V * 9 * 16), "hipMalloc(U)");
             {
-                const int bz_default[4] = {0, 2, 2, 2};   // measured best at 24^3x64, Ls=24
+                const int bz_default[4] = {2, 2, 2, 2};   // measured best at 24^3x64, Ls=24
                 for (int p = 0; p < 4; ++p) {
                     int bz = bz_default[p];
                     if (const char* e = getenv("EOFA_ZBLOCK")) bz = atoi(e);

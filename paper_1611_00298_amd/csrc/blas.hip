@@ -38,35 +38,63 @@ __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ part
     block_store_sum(t, out + slot);
 }
 
-// x += alpha p ; r -= alpha w ; partial |r|^2 ; alpha = sc[i_num] / sc[i_den]
-template <int P, int PX>
-__global__ void __launch_bounds__(256) k_xr_update(void* x, float* xn, const void* p, const float* pn,
-                                                   void* r, float* rn, const void* w, const float* wn,
-                                                   const double* sc, int i_num, int i_den, size_t n5,
-                                                   size_t N, double* partial) {
+// r -= alpha w ; partial |r|^2 ; alpha = sc[i_num] / sc[i_den], also kept in
+// sc[i_save] for the batched solution update
+template <int P>
+__global__ void __launch_bounds__(256) k_r_update(void* r, float* rn, const void* w, const float* wn,
+                                                  double* sc, int i_num, int i_den, int i_save,
+                                                  size_t n5, size_t N, double* partial) {
     using A = typename PT<P>::A;
-    using AX = typename PT<PX>::A;
     const double alpha_d = sc[i_num] / sc[i_den];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[i_save] = alpha_d;
     const A alpha = (A)alpha_d;
     double acc = 0;
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
          n += (size_t)gridDim.x * blockDim.x) {
-        A pv[24], wv[24], rv[24];
-        AX xv[24];
-        ld_spinor<P>(p, pn, N, n, pv);
+        A wv[24], rv[24];
         ld_spinor<P>(w, wn, N, n, wv);
         ld_spinor<P>(r, rn, N, n, rv);
-        ld_spinor<PX>(x, xn, N, n, xv);
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
-            xv[k] += (AX)alpha_d * (AX)pv[k];
-            rv[k] -= alpha * wv[k];
+            rv[k] = fmadd(-alpha, wv[k], rv[k]);
             acc += (double)rv[k] * (double)rv[k];
         }
-        st_spinor<PX>(x, xn, N, n, xv);
         st_spinor<P>(r, rn, N, n, rv);
     }
     block_store_sum(acc, partial + blockIdx.x);
+}
+
+// x += sum_j alpha_j p_j over a batch of saved search directions
+struct PBatch {
+    const void* p[8];
+    const float* pn[8];
+    int slot[8];   // alpha_j = sc[slot[j]]
+    int cnt;
+};
+
+template <int P, int PX>
+__global__ void __launch_bounds__(256) k_x_batch(void* x, float* xn, const PBatch b, const double* sc,
+                                                 size_t n5, size_t N) {
+    using A = typename PT<P>::A;
+    using AX = typename PT<PX>::A;
+    AX al[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) al[j] = j < b.cnt ? (AX)sc[b.slot[j]] : AX(0);
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        AX xv[24];
+        ld_spinor<PX>(x, xn, N, n, xv);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j < b.cnt) {
+                A pv[24];
+                ld_spinor<P>(b.p[j], b.pn[j], N, n, pv);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) xv[k] = fmadd(al[j], (AX)pv[k], xv[k]);
+            }
+        }
+        st_spinor<PX>(x, xn, N, n, xv);
+    }
 }
 
 // partial |f|^2
@@ -144,27 +172,35 @@ hipError_t launch_reduce(const double* partial, int n, double* out, int slot, hi
     return hipGetLastError();
 }
 
-hipError_t launch_xr_update(int prec, void* x, float* xn, const void* p, const float* pn, void* r,
-                            float* rn, const void* w, const float* wn, const double* sc, int i_num,
-                            int i_den, size_t n5, size_t N, double* partial, int nblk,
-                            hipStream_t st) {
+hipError_t launch_r_update(int prec, void* r, float* rn, const void* w, const float* wn, double* sc,
+                           int i_num, int i_den, int i_save, size_t n5, size_t N, double* partial,
+                           int nblk, hipStream_t st) {
     switch (prec) {
-    case P64:
-        hipLaunchKernelGGL((k_xr_update<P64, P64>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
-                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
-        break;
-    case P32:
-        hipLaunchKernelGGL((k_xr_update<P32, P32>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
-                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
-        break;
-    case P16:
-        hipLaunchKernelGGL((k_xr_update<P16, P32>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
-                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
-        break;
-    case PB16:
-        hipLaunchKernelGGL((k_xr_update<PB16, P32>), dim3(nblk), dim3(256), 0, st, x, xn, p, pn, r,
-                           rn, w, wn, sc, i_num, i_den, n5, N, partial);
-        break;
+    case P64: hipLaunchKernelGGL((k_r_update<P64>), dim3(nblk), dim3(256), 0, st, r, rn, w, wn, sc, i_num, i_den, i_save, n5, N, partial); break;
+    case P32: hipLaunchKernelGGL((k_r_update<P32>), dim3(nblk), dim3(256), 0, st, r, rn, w, wn, sc, i_num, i_den, i_save, n5, N, partial); break;
+    case P16: hipLaunchKernelGGL((k_r_update<P16>), dim3(nblk), dim3(256), 0, st, r, rn, w, wn, sc, i_num, i_den, i_save, n5, N, partial); break;
+    case PB16: hipLaunchKernelGGL((k_r_update<PB16>), dim3(nblk), dim3(256), 0, st, r, rn, w, wn, sc, i_num, i_den, i_save, n5, N, partial); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_x_batch(int prec, void* x, float* xn, const void* const* p, const float* const* pn,
+                          const int* slots, int cnt, const double* sc, size_t n5, size_t N, int nblk,
+                          hipStream_t st) {
+    if (cnt < 1 || cnt > 8) return hipErrorInvalidValue;
+    PBatch b;
+    for (int j = 0; j < 8; ++j) {
+        b.p[j] = j < cnt ? p[j] : nullptr;
+        b.pn[j] = j < cnt ? pn[j] : nullptr;
+        b.slot[j] = j < cnt ? slots[j] : 0;
+    }
+    b.cnt = cnt;
+    switch (prec) {
+    case P64: hipLaunchKernelGGL((k_x_batch<P64, P64>), dim3(nblk), dim3(256), 0, st, x, xn, b, sc, n5, N); break;
+    case P32: hipLaunchKernelGGL((k_x_batch<P32, P32>), dim3(nblk), dim3(256), 0, st, x, xn, b, sc, n5, N); break;
+    case P16: hipLaunchKernelGGL((k_x_batch<P16, P32>), dim3(nblk), dim3(256), 0, st, x, xn, b, sc, n5, N); break;
+    case PB16: hipLaunchKernelGGL((k_x_batch<PB16, P32>), dim3(nblk), dim3(256), 0, st, x, xn, b, sc, n5, N); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -569,7 +569,8 @@ __global__ void __launch_bounds__(256, MF == 8 ? 2 : 3) k_hop(const HopArgs a) {
 // the first call), pt <- Dtilde p = (b5 + c5 L) p.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_nrm, void* p,
+__global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_nrm, const void* pold,
+                                                 const float* pold_nrm, void* p,
                                                  float* p_nrm, void* pt, float* pt_nrm,
                                                  const double* sc, int i_new, int i_old, int first,
                                                  int Vh, int Ls, int NS, size_t N, double b5,
@@ -592,7 +593,7 @@ __global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_n
         if (!first) {
             const A beta = (A)(sc[i_new] / sc[i_old]);
             A q[24];
-            ld_spinor<P>(p, p_nrm, N, n, q);
+            ld_spinor<P>(pold, pold_nrm, N, n, q);
 #pragma unroll
             for (int k = 0; k < 24; ++k) v[k] += beta * q[k];
         }
@@ -643,7 +644,8 @@ hipError_t launch_hop(int prec, bool dag, bool hop, const HopArgs& a, int nblk, 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pupdate(int prec, const void* z, const float* zn, void* p, float* pn, void* pt,
+hipError_t launch_pupdate(int prec, const void* z, const float* zn, const void* po, const float* pon,
+                          void* p, float* pn, void* pt,
                           float* ptn, const double* sc, int i_new, int i_old, int first, int Vh,
                           int Ls, int NS, size_t N, double b5, double c5, double mp, double mm,
                           int nblk, hipStream_t st) {
@@ -652,7 +654,7 @@ hipError_t launch_pupdate(int prec, const void* z, const float* zn, void* p, flo
 #define EOFA_CASE(PP)                                                                         \
     case PP: {                                                                                \
         const size_t shm = (size_t)STR * NT * sizeof(typename PT<PP>::A);                     \
-        hipLaunchKernelGGL((k_pupdate<PP>), dim3(nblk), dim3(NT), shm, st, z, zn, p, pn, pt,  \
+        hipLaunchKernelGGL((k_pupdate<PP>), dim3(nblk), dim3(NT), shm, st, z, zn, po, pon, p, pn, pt, \
                            ptn, sc, i_new, i_old, first, Vh, Ls, NS, N, b5, c5, mp, mm);      \
         return hipGetLastError();                                                             \
     }
