@@ -6,7 +6,7 @@ workload (the shape of the paper's 24ID ensemble, Table 1; synthetic random
 SU(3) links, eps = 0.5): both EOFA solves in the Cayley form with even-odd
 CGNR to a true residual of 1e-10 (mixed precision: low-precision inner
 operator, FP64 reductions and reliable updates), the EOFA action, the
-eq. (3.3) force from the two solutions, and a leapfrog momentum/link update
+eq. (3.2) force from the two solutions, and a leapfrog momentum/link update
 followed by the re-ingest of the new links.
 
 Printed: one JSON line with the sustained operator rate (GFLOP/s counted
@@ -34,6 +34,49 @@ FLOPS_DDWF = 1320 + 72 + 72 + 24   # one D_DWF application per 5D site (conventi
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    """sha256 of the sources that define the hopping kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dslash.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1611_00298_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(inner, workload):
+    """HBM bytes per launch of the hopping kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None if
+    there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"k_hop_{inner}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(dev):
+    """2 GiB device-to-device copies: the known-size reference that the
+    FETCH_SIZE / WRITE_SIZE counters are scaled against."""
+    import torch
+    x = torch.ones(512 * 1024 * 1024, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
 
 
 def cpu_baseline(pre, seconds=12.0):
@@ -72,6 +115,8 @@ def main():
     ap.add_argument("--dt", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run 3 x 2 GiB device copies first (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
@@ -84,6 +129,8 @@ def main():
 
     pre = din.preset(args.workload)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        copy_calibration(dev)
     t = lambda a: torch.from_numpy(a).to(dev)
     log(f"bench: generating {args.workload} inputs {pre['L']} Ls={pre['Ls']}")
     U = t(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"]))
@@ -147,7 +194,8 @@ def main():
                                f"Cayley-form even-odd CG solves to 1e-10 + action + force + MD step",
                    "inner_precision": args.inner, "tol": tol, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.inner, args.workload),
                      "kernel": f"k_hop<{args.inner}> (5D hopping + fused 5D ops)",
                      "launches": hq["count"], "avg_ms": avg_ms, "avg_bytes": avg_bytes,
                      "hop_gflops": (1320 * pre["L"][0] * pre["L"][1] * pre["L"][2] * pre["L"][3] // 2

@@ -104,7 +104,7 @@ int eofa_ctx_update_gauge(eofa_ctx_t *ctx, const void *U_dev);
 int dwf_apply(eofa_ctx_t *ctx, double m_plus, double m_minus, int dagger, int eo,
               eofa_prec_t prec, const void *in_dev, void *out_dev);
 
-/* EOFA solves, action and M_EOFA phi (eqs. (2.5), (3.3), (5.1)).
+/* EOFA solves, action and M_EOFA phi (eqs. (2.5), (3.2), (5.1)).
  *   chi_L = H(m1, m1)^-1 Omega_- P_- phi,  chi_R = H(m1, m2)^-1 Omega_+ P_+ phi
  * (H(m2) - Delta_+ P_+ = H(m+ = m1, m- = m2)), computed in the Cayley form
  * chi = Dtilde D_DWF^-1 gamma_5 R_5 v (footnote of Section 5.1) with
@@ -118,7 +118,7 @@ int eofa_solve(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
                const void *x0_L_dev, const void *x0_R_dev, void *chiL_dev, void *chiR_dev,
                void *Mphi_dev, double *S_out, const eofa_solver_t *solver, eofa_stats_t *stats);
 
-/* Pseudofermion force of eq. (3.3):
+/* Pseudofermion force of eq. (3.2):
  *   d^a_{x,mu} S = k chi_L^dag g5 R5 (d^a D_w) chi_L - k chi_R^dag g5 R5 (d^a D_w) chi_R,
  * d^a the derivative along U_mu(x) -> exp(i eps T^a) U_mu(x), T^a = lambda^a/2.
  *   F_dev: F_mu(x) = sum_a T^a d^a S (Hermitian traceless 3x3 per link,

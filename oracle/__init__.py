@@ -227,7 +227,7 @@ def solve_H(lat: Lattice, U, mp, mm, v, tol=1e-12, maxiter=100000):
 
 
 def eofa_chi(lat: Lattice, U, m1, m2, phi, method="cayley", tol=1e-12, maxiter=100000):
-    """(chi_L, chi_R, iters) of eq. (3.3)'s definitions."""
+    """(chi_L, chi_R, iters) of eq. (3.2)'s definitions."""
     chiL = lat.zeros5()
     chiR = lat.zeros5()
     its = np.zeros(2, dtype=np.int32)
@@ -248,7 +248,7 @@ def action(lat: Lattice, m1, m2, phi, chiL, chiR):
 
 
 def force(lat: Lattice, U, m1, m2, chiL, chiR, links=None, want_grad=True):
-    """Force F = sum_a T^a d^a S of eq. (3.3) and the gradient G.
+    """Force F = sum_a T^a d^a S of eq. (3.2) and the gradient G.
 
     links: None (all, arrays shaped like U) or an int array (n, 2) of
     (mu, natural site index) pairs (arrays shaped (n, 3, 3))."""

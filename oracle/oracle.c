@@ -647,7 +647,7 @@ int orc_solve_H(const og_t *g, const double *U, double mp, double mm,
 }
 
 /* ------------------------------------------------------------------ */
-/* EOFA solutions, action and force (Sections 2, 3.1, 3.3)               */
+/* EOFA solutions, action and force (Sections 2, 3.1, 3.3 (force: eq. (3.2)))               */
 /* ------------------------------------------------------------------ */
 
 /* chi_L = H(m1,m1)^-1 Omega_- P_- phi and chi_R = H(m1,m2)^-1 Omega_+ P_+ phi
@@ -740,7 +740,7 @@ static cplx link_variation(const og_t *g, long i, int mu, const cplx *dU,
     return acc;
 }
 
-/* Pseudofermion force of eq. (3.3):
+/* Pseudofermion force of eq. (3.2):
  *   d^a_{x,mu} S = k chi_L^dag g5 R5 (d^a D_w) chi_L - k chi_R^dag g5 R5 (d^a D_w) chi_R
  * with d^a the derivative along U_mu(x) -> exp(i eps T^a) U_mu(x),
  * T^a = lambda^a / 2.  F_mu(x) = sum_a T^a d^a S (Hermitian, traceless).

@@ -1,4 +1,4 @@
-"""EOFA action as a torch.autograd.Function (eqs. (2.5) and (3.3)).
+"""EOFA action as a torch.autograd.Function (eqs. (2.5) and (3.2)).
 
 forward:  S(U) = phi^dag M_EOFA(U) phi, through eofa_solve (two Cayley-form
           CG solves on the GPU).

@@ -282,7 +282,10 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     f += op_flops(h.C);
     c->flops += f * (double)c->n5;
     double bytes = nfields * spinor_bytes(h.prec) * (double)c->n5;
-    if (h.hop) bytes += 72.0 * complex_bytes(lp) * c->Vh;
+    // algorithmic link bytes: the 4V links of one checkerboard hop, 9 complex
+    // numbers each at the field precision (what the kernel reads can be more:
+    // FP32 links or the FP16 rows of the matrix-core path)
+    if (h.hop) bytes += 72.0 * complex_bytes(h.prec) * c->Vh;
     const int ev = timing_begin(c);
     hipchk(launch_hop(h.prec, h.dag, h.hop, a, c->nblk_hop, c->st), "hop kernel");
     timing_end(c, ev, h.hop ? (int)h.prec : C_BLAS, bytes);

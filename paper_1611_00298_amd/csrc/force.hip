@@ -1,4 +1,4 @@
-// force.hip -- EOFA pseudofermion force (eq. (3.3)) and the MD link update.
+// force.hip -- EOFA pseudofermion force (eq. (3.2)) and the MD link update.
 //
 // For a link U_mu(x) the variation of S = phi^dag M_EOFA phi is
 //   k chi_L^dag g5 R5 (dD_w) chi_L - k chi_R^dag g5 R5 (dD_w) chi_R.

@@ -1,7 +1,7 @@
 """Fermion-only EOFA molecular dynamics (Section 3): leapfrog on (U, P).
 
 H = sum tr P^2 + S_EOFA(U).  Each force evaluation is two Cayley-form CG
-solves plus the eq. (3.3) force kernel; the momentum and link updates run
+solves plus the eq. (3.2) force kernel; the momentum and link updates run
 in FP64 in eofa_md_update.
 """
 from __future__ import annotations

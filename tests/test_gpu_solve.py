@@ -1,5 +1,5 @@
 """GPU EOFA solves (Cayley form + even-odd CGNR, Section 5.1), action
-(eq. (2.5)), force (eq. (3.3)) and MD update against the CPU oracle."""
+(eq. (2.5)), force (eq. (3.2)) and MD update against the CPU oracle."""
 import numpy as np
 import pytest
 import scipy.linalg
@@ -14,7 +14,7 @@ C1 = din.preset("c1")
 
 
 def sources(lat, phi, m1, m2):
-    """v_L = Omega_- P_- phi, v_R = Omega_+ P_+ phi (eq. (3.3) definitions)."""
+    """v_L = Omega_- P_- phi, v_R = Omega_+ P_+ phi (eq. (3.2) definitions)."""
     om_m, om_p, k = oracle.omega_k(lat, m1, m2)
     vL, vR = lat.zeros5(), lat.zeros5()
     vL[..., 2:, :] = om_m[:, None, None, None, None, None, None] * phi[None, ..., 2:, :]
@@ -138,7 +138,7 @@ def test_force_with_internal_solve(c1):
 
 
 def test_force_finite_difference_su3(c1):
-    """eq. (3.3) against central differences of S under U -> exp(i d T^a) U."""
+    """eq. (3.2) against central differences of S under U -> exp(i d T^a) U."""
     from paper_1611_00298_amd import Context
     lat, U, phi = c1["lat"], c1["U"], c1["phi"]
     m1, m2 = c1["m1"], c1["m2"]

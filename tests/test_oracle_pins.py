@@ -230,7 +230,7 @@ def dense_eofa(tiny):
 
 def build_M_eofa(lat, U, m1, m2, H1, H12):
     """Dense M_EOFA from the oracle's action routine on unit 4D vectors,
-    with chi_L, chi_R from dense solves with H (eq. (3.3) definitions)."""
+    with chi_L, chi_R from dense solves with H (eq. (3.2) definitions)."""
     shape4 = lat.shape4 + (4, 3)
     n = lat.V * 12
     om_m, om_p, k = oracle.omega_k(lat, m1, m2)
@@ -275,7 +275,7 @@ def test_eq1_determinant_ratio(dense_eofa):
 
 
 def test_mass_split_of_R_operator(dense_eofa):
-    """P7: H(m2) - Delta_+ P_+ = H(m+ = m1, m- = m2) (eq. (2.5), Section 3.3)."""
+    """P7: H(m2) - Delta_+ P_+ = H(m+ = m1, m- = m2) (eq. (2.5); Section 3.3)."""
     lat, U, m1, m2, H1, H12, H2 = dense_eofa
     R5 = np.eye(lat.Ls)[::-1]
     Dp = R5 @ (oracle.chiral_matrix(lat, "dperp", True, m2)
@@ -435,7 +435,7 @@ def test_gauge_covariance():
 
 
 # --------------------------------------------------------------------------
-# P8: eq. (3.3) force against central finite differences
+# P8: eq. (3.2) force against central finite differences
 # --------------------------------------------------------------------------
 
 def test_force_finite_difference():
