@@ -9,7 +9,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libeofa.so")
+LIB_PATH = os.environ.get("EOFA_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libeofa.so")
 
 EOFA_OK, EOFA_EINVAL, EOFA_ENOMEM, EOFA_ENOCONV, EOFA_ENAN, EOFA_EDEVICE = 0, -1, -2, -3, -4, -5
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}

@@ -760,6 +760,10 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             for (int q = ns; q >= 1; --q)
                 if ((q * c->Ls) % 64 == 0) { best = q; break; }
             c->NS = best;
+            if (const char* e = getenv("EOFA_NS")) {   // tuning override: sites per workgroup
+                const int q = atoi(e);
+                if (q >= 1 && q * c->Ls <= 256) c->NS = q;
+            }
             c->nblk_hop = (c->Vh + c->NS - 1) / c->NS;
             c->nblk_blas = blas_blocks(c->n5);
             size_t np = (size_t)2 * c->nblk_hop;
