@@ -7,7 +7,10 @@ SU(3) links, eps = 0.5): both EOFA solves in the Cayley form with even-odd
 CGNR to a true residual of 1e-10 (mixed precision: low-precision inner
 operator, FP64 reductions and reliable updates), the EOFA action, the
 eq. (3.2) force from the two solutions, and a leapfrog momentum/link update
-followed by the re-ingest of the new links.
+followed by the re-ingest of the new links.  Each step starts from the same
+links and momenta (restored and re-ingested inside the timed region), so
+every step does the same work and the FP64 reference solves the same
+system as the mixed-precision one.
 
 Printed: one JSON line with the sustained operator rate (GFLOP/s counted
 with 1320 flops per Wilson hop per 5D site, 72 per bidiagonal 5D op, 144
@@ -140,7 +143,18 @@ def main():
     ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
     solver = dict(tol=tol, inner=args.inner, reliable_delta=args.delta)
 
+    U0, P0 = U.clone(), P.clone()
+
+    def restart():
+        # every step starts from the same configuration: without a gauge
+        # action the fermion-only MD would roughen the links step by step
+        # and the solves would grow harder, so the steps would not repeat
+        U.copy_(U0)
+        P.copy_(P0)
+        ctx.update_gauge(U)
+
     def step(record):
+        restart()
         chiL, chiR, _, S, st = ctx.eofa_solve(phi, m1, m2, want_mphi=False, **solver)
         F, _, _ = ctx.eofa_force(m1, m2, chiL=chiL, chiR=chiR)
         kin = ctx.md_update(U, P, F, dt_p=args.dt, dt_u=args.dt)
@@ -208,6 +222,7 @@ def main():
     }
     if not args.no_fp64_reference:
         log("bench: FP64 reference solve")
+        restart()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         _, _, _, S64, st64 = ctx.eofa_solve(phi, m1, m2, want_mphi=False, tol=tol, inner="fp64")

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
@@ -113,7 +114,7 @@ struct eofa_ctx {
     size_t n5 = 0, N = 0;
     int NS = 0, nblk_hop = 0, nblk_blas = 0;
     int* nbr = nullptr;
-    int* order[4] = {nullptr, nullptr, nullptr, nullptr};   // block traversal order per precision
+    int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
     void* frag = nullptr;        // FP16 link rows for the matrix-core FP16 hop (4 | Ls)
@@ -252,7 +253,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     const int lp = link_prec(h.prec);
     a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
     a.nbr = c->nbr + (size_t)h.par * 8 * c->Vh;
-    a.order = c->order[h.prec];
+    a.sites = c->sites[h.prec];
     if (h.prec == P16 && c->Ls % 4 == 0 && c->use_mfma) {
         if (!c->frag) {
             hipchk(hipMalloc(&c->frag, (size_t)2 * 8 * c->Vh * 96), "hipMalloc(link rows)");
@@ -671,7 +672,7 @@ void free_ctx(eofa_ctx* c) {
     for (auto& kv : c->ws) { hipFree(kv.second.d); if (kv.second.nrm) hipFree(kv.second.nrm); }
     for (auto& kv : c->raw) hipFree(kv.second);
     for (int p = 0; p < 4; ++p) if (c->gauge[p]) hipFree(c->gauge[p]);
-    for (int p = 0; p < 4; ++p) if (c->order[p]) hipFree(c->order[p]);
+    for (int p = 0; p < 4; ++p) if (c->sites[p]) hipFree(c->sites[p]);
     if (c->nbr) hipFree(c->nbr);
     if (c->U_nat) hipFree(c->U_nat);
     if (c->frag) hipFree(c->frag);
@@ -683,28 +684,86 @@ void free_ctx(eofa_ctx* c) {
     delete c;
 }
 
-// Cache-blocked traversal of the workgroups.  XCD x (of 8) processes one
-// contiguous range of logical blocks (see xcd_block); give that range the
-// time slices [x Lt/8, (x+1) Lt/8) and walk them z-block by z-block: for
-// each group of bz z-planes, all of the XCD's time slices, so that the
-// t-neighbours of a site are touched bz planes apart instead of a whole
-// 3D slice apart and are still in that XCD's L2.  Falls back to the
-// natural order when the lattice does not split this way.
-std::vector<int> block_order(const eofa_ctx* c, int bz) {
-    const int P = c->L[0] * c->L[1] / 2;   // checkerboard sites per (z, t) plane
-    const int Lz = c->L[2], Lt = c->L[3];
-    const int nblk = c->nblk_hop;
-    std::vector<int> ord(nblk);
-    for (int i = 0; i < nblk; ++i) ord[i] = i;
-    if (bz <= 0 || P % c->NS != 0 || Lt % 8 != 0 || nblk % 8 != 0) return ord;
-    const int bpp = P / c->NS, tpx = Lt / 8;
-    int l = 0;
-    for (int x = 0; x < 8; ++x)
-        for (int z0 = 0; z0 < Lz; z0 += bz)
-            for (int t = x * tpx; t < (x + 1) * tpx; ++t)
-                for (int z = z0; z < std::min(z0 + bz, Lz); ++z)
-                    for (int b = 0; b < bpp; ++b) ord[l++] = (t * Lz + z) * bpp + b;
+// Cache-blocked traversal of the hopping kernel.  XCD x (of 8) runs one
+// contiguous range of logical blocks (see xcd_block), so the site table is
+// laid out as 8 regions: the lattice is cut into 8 slabs along `split`, one
+// per XCD.  Inside a slab the sites are visited tile by tile; a tile spans
+// the whole x extent and `ty`, `tz`, `tt` along y, z, t (clamped to the
+// slab), except along `sweep`, which the tile walks one slice at a time.
+// Every slice then needs the slices before and after it along `sweep`,
+// which are still in that XCD's L2, and only the tile's faces across the
+// other directions are read again by the neighbouring tile.  Rows of x hold
+// consecutive checkerboard indices, so the table is the same for both
+// parities.  Returns the natural order if the split does not divide.
+struct Tiling { int split, sweep, ext[3]; };   // dims 1 = y, 2 = z, 3 = t
+
+std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
+    const int Vh = c->Vh, NS = c->NS, nslot = c->nblk_hop * NS;
+    std::vector<int> ord;
+    ord.reserve(nslot);
+    const int hx = c->L[0] / 2;   // checkerboard sites per x row
+    const bool ok = T.split >= 1 && T.split <= 3 && T.sweep >= 1 && T.sweep <= 3 && c->L[T.split] % 8 == 0 &&
+                    (c->L[0] % 2 == 0);
+    if (ok) {
+        int lo[4] = {0, 0, 0, 0}, hi[4] = {c->L[0], c->L[1], c->L[2], c->L[3]};
+        int ext[4] = {c->L[0], T.ext[0], T.ext[1], T.ext[2]};
+        for (int d = 1; d < 4; ++d) if (ext[d] < 1) ext[d] = 1;
+        int od[2], k = 0;   // the two non-sweep dims among y, z, t, slower one first
+        for (int d = 3; d >= 1; --d) if (d != T.sweep) od[k++] = d;
+        for (int X = 0; X < 8; ++X) {
+            lo[T.split] = X * (c->L[T.split] / 8);
+            hi[T.split] = lo[T.split] + c->L[T.split] / 8;
+            for (int a0 = lo[od[0]]; a0 < hi[od[0]]; a0 += ext[od[0]])
+                for (int a1 = lo[od[1]]; a1 < hi[od[1]]; a1 += ext[od[1]])
+                    for (int v = lo[T.sweep]; v < hi[T.sweep]; ++v) {
+                        int b[4], e[4];
+                        b[od[0]] = a0; e[od[0]] = std::min(a0 + ext[od[0]], hi[od[0]]);
+                        b[od[1]] = a1; e[od[1]] = std::min(a1 + ext[od[1]], hi[od[1]]);
+                        b[T.sweep] = v; e[T.sweep] = v + 1;
+                        for (int t = b[3]; t < e[3]; ++t)
+                            for (int z = b[2]; z < e[2]; ++z)
+                                for (int y = b[1]; y < e[1]; ++y) {
+                                    const int cb0 = (c->L[0] * (y + c->L[1] * (z + c->L[2] * t))) / 2;
+                                    for (int i = 0; i < hx; ++i) ord.push_back(cb0 + i);
+                                }
+                    }
+        }
+    }
+    if ((int)ord.size() != Vh) {
+        ord.resize(Vh);
+        for (int i = 0; i < Vh; ++i) ord[i] = i;
+    }
+    // the table must be a permutation of the sites: check it before use
+    std::vector<char> seen(Vh, 0);
+    for (int i : ord) {
+        if (i < 0 || i >= Vh || seen[i]) fail(EOFA_EDEVICE, "internal: traversal table is not a permutation");
+        seen[i] = 1;
+    }
+    ord.resize(nslot, Vh);   // padding slots are inactive
     return ord;
+}
+
+// Default tiling per precision (measured at 24^3x64, Ls = 24, and in a
+// model of the per-XCD L2): slabs along z, tiles of 8 y rows by the slab's
+// z planes, walked along t.  The tuning override EOFA_TILE="split,ty,tz,tt,sweep"
+// with dims given as y, z or t replaces it (e.g. "z,8,3,1,t").
+Tiling default_tiling(const eofa_ctx* c, int prec) {
+    (void)prec;
+    Tiling T{0, 3, {8, 1, 1}};
+    if (c->L[2] % 8 == 0) { T.split = 2; T.ext[1] = c->L[2] / 8; }
+    else if (c->L[3] % 8 == 0) { T.split = 3; T.sweep = 3; T.ext[0] = 6; T.ext[1] = 4; }
+    else if (c->L[1] % 8 == 0) { T.split = 1; T.ext[0] = c->L[1] / 8; T.ext[1] = c->L[2]; }
+    if (const char* e = getenv("EOFA_TILE")) {
+        char sp = 0, sw = 0;
+        int ty = 0, tz = 0, tt = 0;
+        if (sscanf(e, "%c,%d,%d,%d,%c", &sp, &ty, &tz, &tt, &sw) == 5) {
+            auto dim = [](char ch) { return ch == 'y' ? 1 : ch == 'z' ? 2 : ch == 't' ? 3 : 0; };
+            T = Tiling{dim(sp), dim(sw), {ty, tz, tt}};
+        } else if (strcmp(e, "none") == 0) {
+            T.split = 0;
+        }
+    }
+    return T;
 }
 
 void load_gauge(eofa_ctx* c, const void* U) {
@@ -753,8 +812,10 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             if (c->b5 == 0.0 || c->beta0 == 0.0) fail(EOFA_EINVAL, "degenerate Moebius parameters");
             c->n5 = (size_t)c->Vh * c->Ls;
             c->N = (c->n5 + 255) / 256 * 256;
-            // workgroup: NS whole 4D sites x Ls; prefer a multiple of 64 work-items
-            int ns = 256 / c->Ls;
+            // workgroup: NS whole 4D sites x Ls; prefer a multiple of 64 work-items.
+            // NS <= 24 keeps the LDS-staged links of the workgroup (FP64:
+            // 24 sites x 8 directions x 144 B) within 28 KB.
+            int ns = std::min(256 / c->Ls, 24);
             if (ns < 1) ns = 1;
             int best = ns;
             for (int q = ns; q >= 1; --q)
@@ -762,7 +823,7 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             c->NS = best;
             if (const char* e = getenv("EOFA_NS")) {   // tuning override: sites per workgroup
                 const int q = atoi(e);
-                if (q >= 1 && q * c->Ls <= 256) c->NS = q;
+                if (q >= 1 && q <= 24 && q * c->Ls <= 256) c->NS = q;
             }
             c->nblk_hop = (c->Vh + c->NS - 1) / c->NS;
             c->nblk_blas = blas_blocks(c->n5);
@@ -778,16 +839,11 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             hipchk(hipMalloc((void**)&c->nbr, sizeof(int) * 2 * 8 * c->Vh), "hipMalloc(nbr)");
             hipchk(hipMalloc(&c->gauge[P64], (size_t)2 * 8 * 9 * c->Vh * 16), "hipMalloc(gauge)");
             hipchk(hipMalloc(&c->U_nat, (size_t)4 * c->V * 9 * 16), "hipMalloc(U)");
-            {
-                const int bz_default[4] = {2, 2, 2, 2};   // measured best at 24^3x64, Ls=24
-                for (int p = 0; p < 4; ++p) {
-                    int bz = bz_default[p];
-                    if (const char* e = getenv("EOFA_ZBLOCK")) bz = atoi(e);
-                    std::vector<int> ord = block_order(c, bz);
-                    hipchk(hipMalloc((void**)&c->order[p], sizeof(int) * ord.size()), "hipMalloc(order)");
-                    hipchk(hipMemcpy(c->order[p], ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice),
-                           "copy order");
-                }
+            for (int p = 0; p < 4; ++p) {
+                const std::vector<int> ord = site_order(c, default_tiling(c, p));
+                hipchk(hipMalloc((void**)&c->sites[p], sizeof(int) * ord.size()), "hipMalloc(site table)");
+                hipchk(hipMemcpy(c->sites[p], ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice),
+                       "copy site table");
             }
             if (const char* e = getenv("EOFA_NO_MFMA")) c->use_mfma = atoi(e) == 0;
             if (const char* e = getenv("EOFA_MFMA_DEPTH")) c->mfma_depth = atoi(e);

@@ -10,12 +10,13 @@
 // Dh = -1/2 sum_mu [(1-gamma_mu) U_mu(x) T+mu + (1+gamma_mu) U_mu(x-mu)^dag T-mu]
 // (with the -1/2 and the boundary signs folded into the stored links), and
 // its adjoint gamma_5 Dh gamma_5 when DAG.  The 4D site's links are shared
-// by its Ls work-items, which read the same addresses.  A, B, C are the
+// by its Ls work-items: the workgroup stages them in LDS once per launch.  A, B, C are the
 // gauge-independent 5D operators of the Moebius/Cayley form (Section 2 and
 // the Section 5.1 even-odd factorisation): Dtilde = b5 + c5 L,
 // M_ee = (4-M5) Dtilde + 1 - L and M_ee^-1, with L or L^T.  Inverses use a
 // weighted Hillis-Steele scan over s in LDS plus a rank-one wrap correction.
-// The stencil is bandwidth-bound: no matrix cores.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace eofa {
@@ -103,27 +104,96 @@ __device__ __forceinline__ void su3_mul(const A (&U)[18], const A (&h)[12], A (&
         }
 }
 
-// One direction's operands, loaded one direction ahead of their use.
+// ---------------------------------------------------------------------------
+// The links of the workgroup's NS sites are staged in LDS once per launch:
+// the Ls work-items of a site then read them from LDS instead of each
+// issuing the same global loads.  The staging loads are issued after the
+// first neighbour-spinor loads so that both latencies overlap (FP64, whose
+// registers hold one direction only, stages first and also keeps the
+// neighbour indices in LDS).  Layout: [NS][8] link records of LB bytes,
+// then [NS][8] neighbour indices (FP64),
+//   P64      : 9 double2 (LB 144)
+//   FP32 link: 9 float2, padded (LB 80) -- the FP32, BF16 and vector FP16 paths
+//   MF       : 8 rows of 8 halves (LB 128), rows 6 and 7 zero (matrix cores)
+// ---------------------------------------------------------------------------
+template <int P, int MF> struct LinkLds {
+    static constexpr int LB = MF ? 128 : (P == P64 ? 144 : 80);
+};
+
+__host__ __device__ constexpr size_t stage_bytes(int lb_bytes, int NS) {
+    return (size_t)NS * 8 * lb_bytes + (size_t)NS * 8 * sizeof(int);
+}
+
+__device__ __forceinline__ int slot_site(const HopArgs& a, int lb, int j) {
+    const int slot = lb * a.NS + j;
+    const int site = a.sites ? a.sites[slot] : slot;
+    return site < a.Vh ? site : 0;   // padding slots read site 0 and discard it
+}
+
+template <int P, int MF>
+__device__ __forceinline__ void stage_links(const HopArgs& a, int lb, unsigned char* lds) {
+    constexpr int LB = LinkLds<P, MF>::LB;
+    const int NS = a.NS, NT = blockDim.x, tid = threadIdx.x;
+    if constexpr (P == P64) {   // FP64 also stages the neighbour indices, after the links
+        int* nbl = reinterpret_cast<int*>(lds + (size_t)NS * 8 * LB);
+        for (int e = tid; e < NS * 8; e += NT) {
+            const int j = e % NS, d = e / NS;
+            nbl[j * 8 + d] = a.nbr[(size_t)d * a.Vh + slot_site(a, lb, j)];
+        }
+    }
+    if constexpr (MF != 0) {
+        // rows of one (d, site) are contiguous in the global table: r fastest
+        for (int e = tid; e < NS * 64; e += NT) {
+            const int r = e & 7, jd = e >> 3;
+            const int j = jd % NS, d = jd / NS;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (r < 6) v = at<uint4>(a.frag, 0, ((uint32_t)d * (uint32_t)a.Vh + (uint32_t)slot_site(a, lb, j)) * 96u + 16u * r);
+            *reinterpret_cast<uint4*>(lds + (j * 8 + d) * LB + 16 * r) = v;
+        }
+    } else if constexpr (P == P64) {
+        const size_t bb = (size_t)a.Vh * 16;
+        for (int e = tid; e < NS * 72; e += NT) {
+            const int j = e % NS, dk = e / NS;
+            const int d = dk / 9, k = dk - 9 * d;
+            *reinterpret_cast<double2*>(lds + (j * 8 + d) * LB + 16 * k) =
+                at<double2>(a.gauge, (size_t)dk * bb, (uint32_t)slot_site(a, lb, j) * 16u);
+        }
+    } else {
+        const size_t bb = (size_t)a.Vh * 8;
+        for (int e = tid; e < NS * 72; e += NT) {
+            const int j = e % NS, dk = e / NS;
+            const int d = dk / 9, k = dk - 9 * d;
+            *reinterpret_cast<float2*>(lds + (j * 8 + d) * LB + 8 * k) =
+                at<float2>(a.gauge, (size_t)dk * bb, (uint32_t)slot_site(a, lb, j) * 8u);
+        }
+    }
+}
+
+// One direction's neighbour spinor, loaded ahead of its use.
 template <int P> struct Stage {
     using A = typename PT<P>::A;
     A psi[24];    // neighbour spinor (16-bit fields: raw values, scale in nrm)
-    A U[18];      // link
     float nrm;
 };
 
-template <int P, int D>
-__device__ __forceinline__ void load_stage(const HopArgs& a, int site, int s, int nb, Stage<P>& st) {
+template <int P>
+__device__ __forceinline__ void load_stage(const HopArgs& a, int s, int nb, Stage<P>& st) {
     const size_t n = (size_t)nb * a.Ls + s;
     if constexpr (P == P16 || P == PB16) st.nrm = ld_spinor_raw<P>(a.in, a.in_nrm, a.N, n, st.psi);
     else ld_spinor<P>(a.in, a.in_nrm, a.N, n, st.psi);
-    ld_link<P>(a.gauge, D, site, a.Vh, st.U);
 }
 
 template <int P, bool DAG, int D>
-__device__ __forceinline__ void compute_stage(const Stage<P>& st, typename PT<P>::A (&acc)[24]) {
+__device__ __forceinline__ void compute_stage(const Stage<P>& st, const unsigned char* lrec,
+                                              typename PT<P>::A (&acc)[24]) {
     using A = typename PT<P>::A;
     constexpr int MU = D & 3;
     constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
+    using L = typename PT<link_prec(P)>::A;
+    const L* ul = reinterpret_cast<const L*>(lrec);
+    A U[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) U[k] = (A)ul[k];
     A h[12];
     project<MU, SG>(st.psi, h);
     if constexpr (P == P16) {
@@ -131,45 +201,59 @@ __device__ __forceinline__ void compute_stage(const Stage<P>& st, typename PT<P>
         for (int k = 0; k < 12; ++k) h[k] *= st.nrm;
     }
     A u[12];
-    su3_mul(st.U, h, u);
+    su3_mul(U, h, u);
     reconstruct<MU, SG>(u, acc);
 }
 
-// all eight directions, operands of direction d+1 in flight while d computes
 template <int P, bool DAG>
-__device__ __forceinline__ void hop_all(const HopArgs& a, int site, int s, typename PT<P>::A (&acc)[24]) {
+__device__ __forceinline__ void compute_stage_rt(const Stage<P>& st, int d, const unsigned char* lrec,
+                                                 typename PT<P>::A (&acc)[24]) {
+    switch (d) {   // d is a compile-time constant after unrolling
+    case 0: compute_stage<P, DAG, 0>(st, lrec, acc); break;
+    case 1: compute_stage<P, DAG, 1>(st, lrec, acc); break;
+    case 2: compute_stage<P, DAG, 2>(st, lrec, acc); break;
+    case 3: compute_stage<P, DAG, 3>(st, lrec, acc); break;
+    case 4: compute_stage<P, DAG, 4>(st, lrec, acc); break;
+    case 5: compute_stage<P, DAG, 5>(st, lrec, acc); break;
+    case 6: compute_stage<P, DAG, 6>(st, lrec, acc); break;
+    default: compute_stage<P, DAG, 7>(st, lrec, acc); break;
+    }
+}
+
+// All eight directions: two neighbour spinors in flight (FP64: one, the
+// registers allow no more), links from LDS.  Every work-item of the
+// workgroup must call this (it contains the staging barrier); padding
+// work-items pass site 0 and discard the result.
+template <int P, bool DAG>
+__device__ __forceinline__ void hop_all(const HopArgs& a, int lb, unsigned char* lds, int site, int sl, int s,
+                                        typename PT<P>::A (&acc)[24]) {
+    constexpr int LB = LinkLds<P, 0>::LB;
+    if constexpr (P == P64) {   // links and neighbour indices already staged by the caller
+        const int* nbl = reinterpret_cast<const int*>(lds + (size_t)a.NS * 8 * LB) + sl * 8;
+        const unsigned char* lr = lds + sl * 8 * LB;
+        Stage<P> st;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            load_stage<P>(a, s, nbl[d], st);
+            compute_stage_rt<P, DAG>(st, d, lr + d * LB, acc);
+        }
+        return;
+    }
+    constexpr int DEPTH = 2;
     int nb[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) nb[d] = a.nbr[(size_t)d * a.Vh + site];
-    if constexpr (P == P64) {   // registers allow one stage in flight
-        Stage<P> st;
-        load_stage<P, 0>(a, site, s, nb[0], st); compute_stage<P, DAG, 0>(st, acc);
-        load_stage<P, 1>(a, site, s, nb[1], st); compute_stage<P, DAG, 1>(st, acc);
-        load_stage<P, 2>(a, site, s, nb[2], st); compute_stage<P, DAG, 2>(st, acc);
-        load_stage<P, 3>(a, site, s, nb[3], st); compute_stage<P, DAG, 3>(st, acc);
-        load_stage<P, 4>(a, site, s, nb[4], st); compute_stage<P, DAG, 4>(st, acc);
-        load_stage<P, 5>(a, site, s, nb[5], st); compute_stage<P, DAG, 5>(st, acc);
-        load_stage<P, 6>(a, site, s, nb[6], st); compute_stage<P, DAG, 6>(st, acc);
-        load_stage<P, 7>(a, site, s, nb[7], st); compute_stage<P, DAG, 7>(st, acc);
-        return;
+    Stage<P> st[DEPTH];
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) load_stage<P>(a, s, nb[d], st[d]);
+    stage_links<P, 0>(a, lb, lds);
+    __syncthreads();
+    const unsigned char* lr = lds + sl * 8 * LB;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        compute_stage_rt<P, DAG>(st[d % DEPTH], d, lr + d * LB, acc);
+        if (d + DEPTH < 8) load_stage<P>(a, s, nb[d + DEPTH], st[d % DEPTH]);
     }
-    Stage<P> s0, s1;
-    load_stage<P, 0>(a, site, s, nb[0], s0);
-    load_stage<P, 1>(a, site, s, nb[1], s1);
-    compute_stage<P, DAG, 0>(s0, acc);
-    load_stage<P, 2>(a, site, s, nb[2], s0);
-    compute_stage<P, DAG, 1>(s1, acc);
-    load_stage<P, 3>(a, site, s, nb[3], s1);
-    compute_stage<P, DAG, 2>(s0, acc);
-    load_stage<P, 4>(a, site, s, nb[4], s0);
-    compute_stage<P, DAG, 3>(s1, acc);
-    load_stage<P, 5>(a, site, s, nb[5], s1);
-    compute_stage<P, DAG, 4>(s0, acc);
-    load_stage<P, 6>(a, site, s, nb[6], s0);
-    compute_stage<P, DAG, 5>(s1, acc);
-    load_stage<P, 7>(a, site, s, nb[7], s1);
-    compute_stage<P, DAG, 6>(s0, acc);
-    compute_stage<P, DAG, 7>(s1, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -250,10 +334,9 @@ __device__ __forceinline__ void reconstruct_f(const float (&u)[12], float f, flo
 struct MStage {
     uint32_t w[12];   // raw FP16 neighbour spinor
     float nrm;
-    uint4 r0, r1;     // link rows lane4 and 4 + lane4
 };
 
-__device__ __forceinline__ void load_mstage(const HopArgs& a, int D, int site, int s, int lane4, int nb, MStage& st) {
+__device__ __forceinline__ void load_mstage(const HopArgs& a, int s, int nb, MStage& st) {
     const uint32_t n = (uint32_t)nb * a.Ls + s;
     const uint32_t off = n * 16u;
 #pragma unroll
@@ -262,20 +345,20 @@ __device__ __forceinline__ void load_mstage(const HopArgs& a, int D, int site, i
         st.w[4 * b] = t.x; st.w[4 * b + 1] = t.y; st.w[4 * b + 2] = t.z; st.w[4 * b + 3] = t.w;
     }
     st.nrm = a.in_nrm[n];
-    const uint32_t loff = ((uint32_t)D * (uint32_t)a.Vh + (uint32_t)site) * 96u;
-    st.r0 = at<uint4>(a.frag, 0, loff + 16u * lane4);
-    st.r1 = make_uint4(0, 0, 0, 0);
-    if (lane4 < 2) st.r1 = at<uint4>(a.frag, 0, loff + 64u + 16u * lane4);
 }
 
+// lrec: the staged link record of this direction (8 rows of 16 bytes)
 template <bool DAG, int D>
-__device__ __forceinline__ void compute_mstage(const MStage& st, float (&acc)[24]) {
+__device__ __forceinline__ void compute_mstage(const MStage& st, const unsigned char* lrec, int lane4,
+                                               float (&acc)[24]) {
     constexpr int MU = D & 3;
     constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
     h2v h[6];
     project_h2<MU, SG>(st.w, h);
-    const h4v A00 = h4_of(st.r0.x, st.r0.y), A01 = h4_of(st.r0.z, st.r0.w);
-    const h4v A10 = h4_of(st.r1.x, st.r1.y), A11 = h4_of(st.r1.z, st.r1.w);
+    const uint4 r0 = *reinterpret_cast<const uint4*>(lrec + 16 * lane4);
+    const uint4 r1 = *reinterpret_cast<const uint4*>(lrec + 64 + 16 * lane4);
+    const h4v A00 = h4_of(r0.x, r0.y), A01 = h4_of(r0.z, r0.w);
+    const h4v A10 = h4_of(r1.x, r1.y), A11 = h4_of(r1.z, r1.w);
     const h2v z2 = {(_Float16)0, (_Float16)0};
     float u[12];
 #pragma unroll
@@ -294,32 +377,39 @@ __device__ __forceinline__ void compute_mstage(const MStage& st, float (&acc)[24
 }
 
 template <bool DAG>
-__device__ __forceinline__ void compute_mstage_rt(const MStage& st, int d, float (&acc)[24]) {
+__device__ __forceinline__ void compute_mstage_rt(const MStage& st, int d, const unsigned char* lrec, int lane4,
+                                                  float (&acc)[24]) {
     switch (d) {   // d is a compile-time constant after unrolling
-    case 0: compute_mstage<DAG, 0>(st, acc); break;
-    case 1: compute_mstage<DAG, 1>(st, acc); break;
-    case 2: compute_mstage<DAG, 2>(st, acc); break;
-    case 3: compute_mstage<DAG, 3>(st, acc); break;
-    case 4: compute_mstage<DAG, 4>(st, acc); break;
-    case 5: compute_mstage<DAG, 5>(st, acc); break;
-    case 6: compute_mstage<DAG, 6>(st, acc); break;
-    default: compute_mstage<DAG, 7>(st, acc); break;
+    case 0: compute_mstage<DAG, 0>(st, lrec, lane4, acc); break;
+    case 1: compute_mstage<DAG, 1>(st, lrec, lane4, acc); break;
+    case 2: compute_mstage<DAG, 2>(st, lrec, lane4, acc); break;
+    case 3: compute_mstage<DAG, 3>(st, lrec, lane4, acc); break;
+    case 4: compute_mstage<DAG, 4>(st, lrec, lane4, acc); break;
+    case 5: compute_mstage<DAG, 5>(st, lrec, lane4, acc); break;
+    case 6: compute_mstage<DAG, 6>(st, lrec, lane4, acc); break;
+    default: compute_mstage<DAG, 7>(st, lrec, lane4, acc); break;
     }
 }
 
-// eight directions with DEPTH directions' operands in flight
+// eight directions with DEPTH directions' neighbour spinors in flight;
+// called by every work-item (staging barrier inside)
 template <bool DAG, int DEPTH>
-__device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int site, int s, int lane4, float (&acc)[24]) {
+__device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int lb, unsigned char* lds, int site, int sl, int s,
+                                             int lane4, float (&acc)[24]) {
+    constexpr int LB = LinkLds<P16, 1>::LB;
     int nb[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) nb[d] = a.nbr[(size_t)d * a.Vh + site];
     MStage st[DEPTH];
 #pragma unroll
-    for (int d = 0; d < DEPTH; ++d) load_mstage(a, d, site, s, lane4, nb[d], st[d]);
+    for (int d = 0; d < DEPTH; ++d) load_mstage(a, s, nb[d], st[d]);
+    stage_links<P16, 1>(a, lb, lds);
+    __syncthreads();
+    const unsigned char* lr = lds + sl * 8 * LB;
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
-        compute_mstage_rt<DAG>(st[d % DEPTH], d, acc);
-        if (d + DEPTH < 8) load_mstage(a, d + DEPTH, site, s, lane4, nb[d + DEPTH], st[d % DEPTH]);
+        compute_mstage_rt<DAG>(st[d % DEPTH], d, lr + d * LB, lane4, acc);
+        if (d + DEPTH < 8) load_mstage(a, s, nb[d + DEPTH], st[d % DEPTH]);
     }
 }
 
@@ -451,7 +541,7 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 }
 
 template <int P, bool DAG, bool HOP, int MF>
-__global__ void __launch_bounds__(256, MF == 8 ? 2 : 3) k_hop(const HopArgs a) {
+__global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
     using A = typename PT<P>::A;
     extern __shared__ unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
@@ -462,7 +552,8 @@ __global__ void __launch_bounds__(256, MF == 8 ? 2 : 3) k_hop(const HopArgs a) {
     const int sl = tid / Ls;
     const int s = tid - sl * Ls;
     const int lb = xcd_block(gridDim.x);
-    const int site = (a.order ? a.order[lb] : lb) * a.NS + sl;
+    const int slot = lb * a.NS + sl;
+    const int site = a.sites ? a.sites[slot] : slot;
     const bool active = site < a.Vh;
     const size_t n = (size_t)site * Ls + s;
     const A mp = (A)a.mp, mm = (A)a.mm;
@@ -471,17 +562,20 @@ __global__ void __launch_bounds__(256, MF == 8 ? 2 : 3) k_hop(const HopArgs a) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = 0;
     if (HOP) {
-        if constexpr (MF) {
-            // matrix-core path: every lane takes part (the MFMA needs the
-            // whole wave); inactive lanes read site 0 and discard it
-            hop_all_mfma<DAG, MF>(a, active ? site : 0, s, tid & 3, v);
-            if (!active) {
-#pragma unroll
-                for (int k = 0; k < 24; ++k) v[k] = 0;
-            }
-        } else if (active) {
-            hop_all<P, DAG>(a, site, s, v);
+        // every work-item takes part (staging barrier; the MFMA needs the
+        // whole wave); padding work-items read site 0 and discard it
+        if constexpr (P == P64) {
+            stage_links<P, 0>(a, lb, smem_raw);
+            __syncthreads();
         }
+        if constexpr (MF) hop_all_mfma<DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
+        else if constexpr (P == P64) { if (active) hop_all<P, DAG>(a, lb, smem_raw, site, sl, s, v); }
+        else hop_all<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
+        if (!active) {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] = 0;
+        }
+        __syncthreads();   // the epilogue reuses the staged LDS area
     }
     if (HOP) {
         A ch = (A)a.ch;
@@ -615,15 +709,17 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     const int NT = a.NS * a.Ls;
     const bool need_lds = HOP ? (a.opA.kind != 0 || a.opC.kind != 0 || (a.aux && a.opB.kind != 0))
                               : (a.opB.kind != 0 || a.opC.kind != 0);
-    const size_t shm = need_lds ? (size_t)STR * NT * sizeof(A) : 0;
+    const size_t tile = need_lds ? (size_t)STR * NT * sizeof(A) : 0;
     if constexpr (P == P16 && HOP) {
         if (a.frag) {
-            if (a.depth >= 8) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 8>), dim3(nblk), dim3(NT), shm, st, a);
+            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 1>::LB, a.NS));
+            if (a.depth >= 4) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 4>), dim3(nblk), dim3(NT), shm, st, a);
             else if (a.depth == 3) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 3>), dim3(nblk), dim3(NT), shm, st, a);
             else hipLaunchKernelGGL((k_hop<P, DAG, HOP, 2>), dim3(nblk), dim3(NT), shm, st, a);
             return hipGetLastError();
         }
     }
+    const size_t shm = HOP ? std::max(tile, stage_bytes(LinkLds<P, 0>::LB, a.NS)) : tile;
     hipLaunchKernelGGL((k_hop<P, DAG, HOP, 0>), dim3(nblk), dim3(NT), shm, st, a);
     return hipGetLastError();
 }

@@ -238,7 +238,7 @@ struct HopArgs {
     const void* aux2; const float* aux2_nrm;
     const void* gauge;   // links of the output parity, [8][9][Vh]
     const int* nbr;      // neighbour cb index of the output parity, [8][Vh]
-    const int* order;    // traversal order: logical block -> block of NS sites (nullable)
+    const int* sites;    // traversal: slot lb*NS + sl -> output site, >= Vh for padding (nullable)
     const void* frag;    // FP16 link rows for the matrix-core path, [8][Vh][6][8] (nullable)
     int depth;           // directions of operands kept in flight (matrix-core path)
     int Vh, Ls, NS;
