@@ -34,7 +34,7 @@ def _want(t, shape, name):
     return t
 
 
-def make_solver(tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.1) -> Solver:
+def make_solver(tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.3) -> Solver:
     return Solver(float(tol), int(maxiter), PREC[inner], float(reliable_delta))
 
 
@@ -94,7 +94,7 @@ class Context:
         return out
 
     # -- eofa_solve ------------------------------------------------------------
-    def eofa_solve(self, phi, m1, m2, tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.1,
+    def eofa_solve(self, phi, m1, m2, tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.3,
                    x0=None, want_mphi=True, allow_noconv=False):
         """Returns (chi_L, chi_R, M_EOFA phi or None, S, stats dict)."""
         _want(phi, self.shape_phi, "phi")
@@ -117,7 +117,7 @@ class Context:
 
     # -- eofa_force ------------------------------------------------------------
     def eofa_force(self, m1, m2, phi=None, chiL=None, chiR=None, want_grad=False, tol=1e-10,
-                   maxiter=20000, inner="fp64", reliable_delta=0.1):
+                   maxiter=20000, inner="fp64", reliable_delta=0.3):
         """Returns (F, G or None, stats dict)."""
         _want(phi, self.shape_phi, "phi")
         _want(chiL, self.shape5, "chi_L")

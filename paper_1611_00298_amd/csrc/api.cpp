@@ -48,7 +48,7 @@ hipError_t launch_zero(int prec, void* f, float* fn, size_t n5, size_t N, int nb
 hipError_t launch_ingest_gauge(const void* U, void* G, int* nbr, const int L[4], int Ls, int aperiodic,
                                hipStream_t st);
 hipError_t launch_gauge_convert(int po, const void* in, void* out, size_t n, hipStream_t st);
-hipError_t launch_gauge_frag(const void* in, void* out, int Vh, hipStream_t st);
+hipError_t launch_gauge_h16(const void* in, void* out, int Vh, hipStream_t st);
 hipError_t launch_nat5_to_dev(const void* nat, void* de, void* dodd, const int L[4], int Ls, size_t N,
                               hipStream_t st);
 hipError_t launch_dev_to_nat5(void* nat, const void* de, const void* dodd, const int L[4], int Ls,
@@ -117,7 +117,7 @@ struct eofa_ctx {
     int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
-    void* frag = nullptr;        // FP16 link rows for the matrix-core FP16 hop (4 | Ls)
+    void* frag = nullptr;        // compact FP16 links for the matrix-core FP16 hop (4 | Ls)
     double* om = nullptr;
     std::vector<double> om_h;
     double* partial = nullptr;
@@ -231,6 +231,9 @@ struct HopCall {
     double ch = 1.0, ca = 1.0, cr = 1.0;
     double mp = 0, mm = 0;
     double* partial = nullptr;
+    // ch and ca scaled on the device by sc[s_num] / sc[s_den] (saved to sc[s_alpha])
+    bool dev_alpha = false;
+    int s_num = 0, s_den = 0, s_alpha = -1;
 };
 
 void run_hop(eofa_ctx* c, const HopCall& h) {
@@ -256,10 +259,10 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.sites = c->sites[h.prec];
     if (h.prec == P16 && c->Ls % 4 == 0 && c->use_mfma) {
         if (!c->frag) {
-            hipchk(hipMalloc(&c->frag, (size_t)2 * 8 * c->Vh * 96), "hipMalloc(link rows)");
-            hipchk(launch_gauge_frag(c->gauge[P64], c->frag, c->Vh, c->st), "link rows");
+            hipchk(hipMalloc(&c->frag, (size_t)2 * 8 * c->Vh * 36), "hipMalloc(FP16 links)");
+            hipchk(launch_gauge_h16(c->gauge[P64], c->frag, c->Vh, c->st), "FP16 links");
         }
-        a.frag = (const char*)c->frag + (size_t)h.par * 8 * c->Vh * 96;
+        a.frag = (const char*)c->frag + (size_t)h.par * 8 * c->Vh * 36;
         a.depth = c->mfma_depth;
     }
     a.Vh = c->Vh;
@@ -275,6 +278,12 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.ca = h.ca;
     a.cr = h.cr;
     a.partial = h.partial;
+    if (h.dev_alpha) {
+        a.dsc = c->sc;
+        a.s_num = h.s_num;
+        a.s_den = h.s_den;
+        a.s_alpha = h.s_alpha;
+    }
     // bookkeeping: flops (fixed convention) and algorithmic bytes
     double f = 0, nfields = 1;
     if (h.hop) f += 1320.0 + op_flops(h.A), nfields += 1;
@@ -317,6 +326,14 @@ double read_slot(eofa_ctx* c, int slot) {
            "hipMemcpy(scalar)");
     hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
     return c->pinned[slot];
+}
+
+// slots [first, first + n) to the host (one synchronisation)
+const double* read_slots(eofa_ctx* c, int first, int n) {
+    hipchk(hipMemcpyAsync(c->pinned + first, c->sc + first, sizeof(double) * n, hipMemcpyDeviceToHost, c->st),
+           "hipMemcpy(scalars)");
+    hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    return c->pinned + first;
 }
 
 double norm2(eofa_ctx* c, const Half& f, int slot) {
@@ -364,6 +381,19 @@ void schur_k4(eofa_ctx* c, int prec, const Half& tmp, const Half& in, Half& out,
     HopCall h;
     h.prec = prec; h.dag = true; h.par = 1; h.in = &tmp; h.out = &out; h.A = Dt(c, 1); h.ch = -1.0;
     h.aux = &in; h.B = Mee(c, 1); h.ca = 1.0; h.mp = mp; h.mm = mm; h.partial = partial;
+    run_hop(c, h);
+}
+
+// K4 with the CG update folded in:
+//   z <- z - alpha Mhat^dag w = z - alpha M_ee^dag w + alpha Dtilde^dag Dh^dag_oe tmp_e,
+// alpha = sc[s_num] / sc[s_den] read on the device and saved to sc[s_alpha]  (+ |z|^2 partials)
+void schur_k4_update(eofa_ctx* c, int prec, const Half& tmp, const Half& w, Half& z, double mp, double mm,
+                     int s_num, int s_den, int s_alpha, double* partial) {
+    HopCall h;
+    h.prec = prec; h.dag = true; h.par = 1; h.in = &tmp; h.out = &z; h.A = Dt(c, 1); h.ch = 1.0;
+    h.aux = &w; h.B = Mee(c, 1); h.ca = -1.0; h.aux2 = &z; h.cr = 1.0; h.mp = mp; h.mm = mm;
+    h.partial = partial;
+    h.dev_alpha = true; h.s_num = s_num; h.s_den = s_den; h.s_alpha = s_alpha;
     run_hop(c, h);
 }
 
@@ -454,6 +484,58 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
                           cur, 1, c->Vh, c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
     double rmax = std::sqrt(rr);
     int k = 0;
+    if (mixed) {
+        // Low-precision iterations keep z = Mhat^dag r by its own recursion
+        // z <- z - alpha Mhat^dag w (folded into K4, so r is not stored);
+        // |r|^2 follows |r_{k+1}|^2 = |r_k|^2 - alpha |z_k|^2 (exact in exact
+        // arithmetic, since (r_k, Mhat p_k) = (z_k, p_k) = |z_k|^2).  Reliable
+        // updates replace the estimate by the FP64 true residual and z by
+        // Mhat^dag of it; convergence is only declared on a true residual.
+        double rr_est = rr;
+        while (res.iters < maxiter) {
+            Half& p = *pr[k % XBATCH];
+            schur_k1(c, prec, pt, tmp, mp, mm);
+            schur_k2(c, prec, tmp, p, w, mp, mm, c->partial);
+            reduce(c, nb, S_WW);
+            schur_k3(c, prec, w, tmp, mp, mm);
+            schur_k4_update(c, prec, tmp, w, z, mp, mm, cur, S_WW, S_ALPHA + k % XBATCH, c->partial);
+            reduce(c, nb, nxt);
+            res.iters++;
+            const double* sv = read_slots(c, S_WW, 3);
+            const double ww = sv[S_WW - S_WW], zz = sv[cur - S_WW];
+            check_finite(ww, "|Mhat p|^2");
+            check_finite(sv[nxt - S_WW], "|z|^2");
+            rr_est -= zz / ww * zz;
+            const double rn = std::sqrt(std::max(rr_est, 0.0));
+            if (rn <= delta * rmax || rn <= thresh) {
+                // reliable update: fold the directions into x_lo, x_lo into x, recompute r in FP64
+                flush(k);
+                hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+                rr = true_residual();
+                check_finite(rr, "true residual");
+                res.reliable++;
+                rmax = std::sqrt(rr);
+                rr_est = rr;
+                if (rmax <= thresh) { res.converged = true; break; }
+                convert(c, r64, r);
+                schur_k3(c, prec, r, tmp, mp, mm);
+                schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
+                reduce(c, nb, nxt);
+            }
+            if (k - pending0 + 1 == XBATCH) flush(k);
+            if (res.iters >= maxiter) { flush(k); break; }
+            Half& pn1 = *pr[(k + 1) % XBATCH];
+            hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pn1.d, pn1.nrm, pt.d, pt.nrm, c->sc, nxt, cur, 0,
+                                  c->Vh, c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+            c->flops += 72.0 * (double)c->n5 + 48.0 * (double)c->n5;
+            std::swap(cur, nxt);
+            ++k;
+        }
+        if (!res.converged)
+            hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+        return res;
+    }
+    // FP64: plain CGNR with the recursively updated residual r
     while (res.iters < maxiter) {
         Half& p = *pr[k % XBATCH];
         // w = Mhat p, |w|^2
@@ -472,24 +554,11 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
         res.iters++;
         rr = read_slot(c, S_RR);
         check_finite(rr, "residual norm");
-        const double rn = std::sqrt(rr);
-        bool stop = false;
-        if (mixed && (rn <= delta * rmax || rn <= thresh)) {
-            // reliable update: fold the directions into x_lo, x_lo into x, recompute r in FP64
-            flush(k);
-            hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
-            rr = true_residual();
-            check_finite(rr, "true residual");
-            res.reliable++;
-            rmax = std::sqrt(rr);
-            if (rmax <= thresh) { res.converged = true; stop = true; }
-            else convert(c, r64, r);
-        } else if (!mixed && rn <= thresh) {
+        if (std::sqrt(rr) <= thresh) {
             flush(k);
             res.converged = true;
-            stop = true;
+            break;
         }
-        if (stop) break;
         if (k - pending0 + 1 == XBATCH) flush(k);
         if (res.iters >= maxiter) { flush(k); break; }
         // z = Mhat^dag r, |z|^2 ; p_{k+1} = z + beta p_k ; pt = Dtilde p_{k+1}
@@ -503,8 +572,6 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
         std::swap(cur, nxt);
         ++k;
     }
-    if (mixed && !res.converged)
-        hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
     return res;
 }
 
@@ -773,7 +840,7 @@ void load_gauge(eofa_ctx* c, const void* U) {
     const size_t nc = (size_t)2 * 8 * 9 * c->Vh;
     for (int p = 1; p < 4; ++p)
         if (c->gauge[p]) hipchk(launch_gauge_convert(p, c->gauge[P64], c->gauge[p], nc, c->st), "gauge convert");
-    if (c->frag) hipchk(launch_gauge_frag(c->gauge[P64], c->frag, c->Vh, c->st), "link rows");
+    if (c->frag) hipchk(launch_gauge_h16(c->gauge[P64], c->frag, c->Vh, c->st), "FP16 links");
 }
 
 }  // namespace

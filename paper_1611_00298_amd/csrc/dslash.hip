@@ -142,12 +142,22 @@ __device__ __forceinline__ void stage_links(const HopArgs& a, int lb, unsigned c
         }
     }
     if constexpr (MF != 0) {
-        // rows of one (d, site) are contiguous in the global table: r fastest
+        // expand the compact FP16 link (9 (re, im) half pairs) into the rows
+        // of its real 6x6 form: row 2a   = (Ur_ab, -Ui_ab) for b = 0..2, 0,
+        //                       row 2a+1 = (Ui_ab,  Ur_ab) for b = 0..2, 0;
+        // rows 6 and 7 are zero.  Work-item e builds row e & 7 of record e >> 3.
+        const uint32_t* g = reinterpret_cast<const uint32_t*>(a.frag);
         for (int e = tid; e < NS * 64; e += NT) {
             const int r = e & 7, jd = e >> 3;
             const int j = jd % NS, d = jd / NS;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (r < 6) v = at<uint4>(a.frag, 0, ((uint32_t)d * (uint32_t)a.Vh + (uint32_t)slot_site(a, lb, j)) * 96u + 16u * r);
+            if (r < 6) {
+                const uint32_t* w = g + ((size_t)d * a.Vh + slot_site(a, lb, j)) * 9 + 3 * (r >> 1);
+                const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+                if (r & 1) v = make_uint4(__builtin_amdgcn_alignbit(w0, w0, 16), __builtin_amdgcn_alignbit(w1, w1, 16),
+                                          __builtin_amdgcn_alignbit(w2, w2, 16), 0u);
+                else v = make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
+            }
             *reinterpret_cast<uint4*>(lds + (j * 8 + d) * LB + 16 * r) = v;
         }
     } else if constexpr (P == P64) {
@@ -577,8 +587,13 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
         }
         __syncthreads();   // the epilogue reuses the staged LDS area
     }
+    double alpha = 1.0;
+    if (a.dsc) {
+        alpha = a.dsc[a.s_num] / a.dsc[a.s_den];
+        if (a.s_alpha >= 0 && blockIdx.x == 0 && tid == 0) a.dsc[a.s_alpha] = alpha;
+    }
     if (HOP) {
-        A ch = (A)a.ch;
+        A ch = (A)(a.ch * alpha);
         bool aux2_done = false;
         if (a.aux2 && a.opA.kind == 0) {   // fold cr * aux2 in before the 5D ops (A = 1)
             A x[24];
@@ -606,7 +621,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
 #pragma unroll
                 for (int k = 0; k < 24; ++k) x[k] = 0;
             }
-            const A ca = (A)a.ca;
+            const A ca = (A)(a.ca * alpha);
             if (a.opB.kind == 1) {
                 put_row(lds, tid, x);
                 __syncthreads();
@@ -631,9 +646,9 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
         // local 5D operator: out = C(ca * B(aux)) + cr * aux2
         if (active) ld_spinor<P>(a.aux, a.aux_nrm, a.N, n, v);
         if (a.opB.kind != 0 || a.opC.kind != 0) {
-            column_phase(lds, tid, sl, s, Ls, v, a.opB, (A)a.ca, a.opC, mp, mm);
+            column_phase(lds, tid, sl, s, Ls, v, a.opB, (A)(a.ca * alpha), a.opC, mp, mm);
         } else {
-            const A ca = (A)a.ca;
+            const A ca = (A)(a.ca * alpha);
 #pragma unroll
             for (int k = 0; k < 24; ++k) v[k] *= ca;
         }
@@ -649,8 +664,11 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
     if (a.partial) {
         double x = 0;
         if (active) {
+            // per work-item sum in the arithmetic type, workgroup and global sums in FP64
+            A q = 0;
 #pragma unroll
-            for (int k = 0; k < 24; ++k) x += (double)v[k] * (double)v[k];
+            for (int k = 0; k < 24; ++k) q = fmadd(v[k], v[k], q);
+            x = (double)q;
         }
         x = block_sum(x, red);
         if (tid == 0) a.partial[blockIdx.x] = x;   // order-independent slot

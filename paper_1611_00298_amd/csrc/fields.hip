@@ -74,30 +74,18 @@ __global__ void k_gauge_convert(const double2* __restrict__ in, void* __restrict
     }
 }
 
-// FP64 links -> FP16 rows of the real 6x6 form of each link (see the
-// matrix-core hop in dslash.hip), [p][d][Vh][6 rows][8 halves], columns 6, 7
-// zero.  One work-item per (p, d, cb).
-__global__ void k_gauge_frag(const double2* __restrict__ in, uint4* __restrict__ out, int Vh) {
+// FP64 links -> compact FP16 links for the matrix-core hop, [p][d][Vh][9]
+// complex numbers as (re, im) half pairs (36 bytes per link; the hop expands
+// them into the rows of the real 6x6 form when it stages them in LDS).
+// One work-item per (p, d, cb).
+__global__ void k_gauge_h16(const double2* __restrict__ in, uint32_t* __restrict__ out, int Vh) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * 8 * Vh) return;
     const int pd = t / Vh, cb = t - pd * Vh;
-    double ur[9], ui[9];
+    uint32_t* o = out + ((size_t)pd * Vh + cb) * 9;
     for (int k = 0; k < 9; ++k) {
         const double2 u = in[((size_t)pd * 9 + k) * Vh + cb];
-        ur[k] = u.x; ui[k] = u.y;
-    }
-    uint4* o = out + ((size_t)pd * Vh + cb) * 6;
-    for (int a = 0; a < 3; ++a) {
-        float re[8], im[8];
-        for (int b = 0; b < 3; ++b) {
-            re[2 * b] = (float)ur[3 * a + b];  re[2 * b + 1] = (float)-ui[3 * a + b];
-            im[2 * b] = (float)ui[3 * a + b];  im[2 * b + 1] = (float)ur[3 * a + b];
-        }
-        re[6] = re[7] = im[6] = im[7] = 0.0f;
-        o[2 * a] = make_uint4(f2h(re[0]) | (f2h(re[1]) << 16), f2h(re[2]) | (f2h(re[3]) << 16),
-                              f2h(re[4]) | (f2h(re[5]) << 16), f2h(re[6]) | (f2h(re[7]) << 16));
-        o[2 * a + 1] = make_uint4(f2h(im[0]) | (f2h(im[1]) << 16), f2h(im[2]) | (f2h(im[3]) << 16),
-                                  f2h(im[4]) | (f2h(im[5]) << 16), f2h(im[6]) | (f2h(im[7]) << 16));
+        o[k] = f2h((float)u.x) | (f2h((float)u.y) << 16);
     }
 }
 
@@ -260,9 +248,9 @@ hipError_t launch_eofa_source(const void* phi, const double* om, void* bLe, void
     return hipGetLastError();
 }
 
-hipError_t launch_gauge_frag(const void* in, void* out, int Vh, hipStream_t st) {
+hipError_t launch_gauge_h16(const void* in, void* out, int Vh, hipStream_t st) {
     const int n = 2 * 8 * Vh;
-    hipLaunchKernelGGL(k_gauge_frag, dim3((n + 255) / 256), dim3(256), 0, st, (const double2*)in, (uint4*)out, Vh);
+    hipLaunchKernelGGL(k_gauge_h16, dim3((n + 255) / 256), dim3(256), 0, st, (const double2*)in, (uint32_t*)out, Vh);
     return hipGetLastError();
 }
 

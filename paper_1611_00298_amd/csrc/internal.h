@@ -239,7 +239,7 @@ struct HopArgs {
     const void* gauge;   // links of the output parity, [8][9][Vh]
     const int* nbr;      // neighbour cb index of the output parity, [8][Vh]
     const int* sites;    // traversal: slot lb*NS + sl -> output site, >= Vh for padding (nullable)
-    const void* frag;    // FP16 link rows for the matrix-core path, [8][Vh][6][8] (nullable)
+    const void* frag;    // compact FP16 links for the matrix-core path, [8][Vh][9] (re, im) halves (nullable)
     int depth;           // directions of operands kept in flight (matrix-core path)
     int Vh, Ls, NS;
     size_t N;
@@ -247,6 +247,10 @@ struct HopArgs {
     Op5 opA, opB, opC;
     double ch, ca, cr;
     double* partial;
+    // optional device scalar: ch and ca are multiplied by alpha =
+    // dsc[s_num] / dsc[s_den], which is also stored to dsc[s_alpha] (>= 0)
+    double* dsc;
+    int s_num, s_den, s_alpha;
 };
 
 }  // namespace eofa
