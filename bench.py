@@ -71,13 +71,16 @@ def measured_traffic(inner, workload):
 
 
 def copy_calibration(dev):
-    """2 GiB device-to-device copies: the known-size reference that the
-    FETCH_SIZE / WRITE_SIZE counters are scaled against."""
+    """Known-size references for the FETCH_SIZE / WRITE_SIZE counters: each
+    of the three rounds runs a 2 GiB device-to-device copy (the runtime's
+    copy kernel) and a 2 GiB elementwise kernel (y = 1 * x, ordinary vector
+    loads and stores like the library's kernels); each reads and writes 2 GiB."""
     import torch
     x = torch.ones(512 * 1024 * 1024, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
     for _ in range(3):
         y.copy_(x)
+        torch.mul(x, 1.0, out=y)
     torch.cuda.synchronize()
     del x, y
 

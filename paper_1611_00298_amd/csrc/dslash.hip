@@ -153,7 +153,8 @@ __device__ __forceinline__ void stage_links(const HopArgs& a, int lb, unsigned c
             uint4 v = make_uint4(0, 0, 0, 0);
             if (r < 6) {
                 const uint32_t* w = g + ((size_t)d * a.Vh + slot_site(a, lb, j)) * 9 + 3 * (r >> 1);
-                const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+                const uint32_t w0 = __builtin_nontemporal_load(w), w1 = __builtin_nontemporal_load(w + 1),
+                               w2 = __builtin_nontemporal_load(w + 2);   // read once per launch
                 if (r & 1) v = make_uint4(__builtin_amdgcn_alignbit(w0, w0, 16), __builtin_amdgcn_alignbit(w1, w1, 16),
                                           __builtin_amdgcn_alignbit(w2, w2, 16), 0u);
                 else v = make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
@@ -597,7 +598,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
         bool aux2_done = false;
         if (a.aux2 && a.opA.kind == 0) {   // fold cr * aux2 in before the 5D ops (A = 1)
             A x[24];
-            if (active) ld_spinor<P>(a.aux2, a.aux2_nrm, a.N, n, x);
+            if (active) ld_spinor<P, true>(a.aux2, a.aux2_nrm, a.N, n, x);
             else {
 #pragma unroll
                 for (int k = 0; k < 24; ++k) x[k] = 0;
@@ -616,7 +617,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
         }
         if (a.aux) {
             A x[24];
-            if (active) ld_spinor<P>(a.aux, a.aux_nrm, a.N, n, x);
+            if (active) ld_spinor<P, true>(a.aux, a.aux_nrm, a.N, n, x);
             else {
 #pragma unroll
                 for (int k = 0; k < 24; ++k) x[k] = 0;
@@ -637,7 +638,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
         }
         if (a.aux2 && !aux2_done && active) {
             A x[24];
-            ld_spinor<P>(a.aux2, a.aux2_nrm, a.N, n, x);
+            ld_spinor<P, true>(a.aux2, a.aux2_nrm, a.N, n, x);
             const A cr = (A)a.cr;
 #pragma unroll
             for (int k = 0; k < 24; ++k) v[k] = fmadd(cr, x[k], v[k]);
@@ -654,13 +655,13 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
         }
         if (a.aux2 && active) {
             A x[24];
-            ld_spinor<P>(a.aux2, a.aux2_nrm, a.N, n, x);
+            ld_spinor<P, true>(a.aux2, a.aux2_nrm, a.N, n, x);
             const A cr = (A)a.cr;
 #pragma unroll
             for (int k = 0; k < 24; ++k) v[k] = fmadd(cr, x[k], v[k]);
         }
     }
-    if (active) st_spinor<P>(a.out, a.out_nrm, a.N, n, v);
+    if (active) st_spinor<P, true>(a.out, a.out_nrm, a.N, n, v);
     if (a.partial) {
         double x = 0;
         if (active) {

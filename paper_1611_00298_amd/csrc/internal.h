@@ -73,7 +73,22 @@ __device__ __forceinline__ T& at_mut(void* base, size_t blk_bytes, uint32_t off)
     return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + blk_bytes + off);
 }
 
-template <int P>
+// 16-byte block access; NT = non-temporal (streaming) hint for data that is
+// touched once, so that it does not displace reused neighbour data in L2
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ uint4 ld16(const void* base, size_t blk, uint32_t off) {
+    const u32x4_t* q = reinterpret_cast<const u32x4_t*>(reinterpret_cast<const char*>(base) + blk + off);
+    u32x4_t v = NT ? __builtin_nontemporal_load(q) : *q;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <bool NT>
+__device__ __forceinline__ void st16(void* base, size_t blk, uint32_t off, uint4 t) {
+    u32x4_t* q = reinterpret_cast<u32x4_t*>(reinterpret_cast<char*>(base) + blk + off);
+    u32x4_t v = {t.x, t.y, t.z, t.w};
+    if (NT) __builtin_nontemporal_store(v, q); else *q = v;
+}
+template <int P, bool NT = false>
 __device__ __forceinline__ void ld_spinor(const void* __restrict__ base, const float* __restrict__ nrm,
                                           size_t N, size_t n, typename PT<P>::A (&v)[24]) {
     const uint32_t off = (uint32_t)n * 16u;
@@ -81,21 +96,21 @@ __device__ __forceinline__ void ld_spinor(const void* __restrict__ base, const f
     if constexpr (P == P64) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            const double2 t = at<double2>(base, c * bb, off);
+            const double2 t = __builtin_bit_cast(double2, ld16<NT>(base, c * bb, off));
             v[2 * c] = t.x; v[2 * c + 1] = t.y;
         }
     } else if constexpr (P == P32) {
 #pragma unroll
         for (int b = 0; b < 6; ++b) {
-            const float4 t = at<float4>(base, b * bb, off);
+            const float4 t = __builtin_bit_cast(float4, ld16<NT>(base, b * bb, off));
             v[4 * b] = t.x; v[4 * b + 1] = t.y; v[4 * b + 2] = t.z; v[4 * b + 3] = t.w;
         }
     } else {
         float sc = 1.0f;
-        if constexpr (P == P16) sc = nrm[n];
+        if constexpr (P == P16) sc = NT ? __builtin_nontemporal_load(nrm + n) : nrm[n];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const uint4 t = at<uint4>(base, b * bb, off);
+            const uint4 t = ld16<NT>(base, b * bb, off);
             uint32_t w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -111,25 +126,27 @@ __device__ __forceinline__ void ld_spinor(const void* __restrict__ base, const f
     }
 }
 
-template <int P>
+template <int P, bool NT = false>
 __device__ __forceinline__ void st_spinor(void* __restrict__ base, float* __restrict__ nrm,
                                           size_t N, size_t n, const typename PT<P>::A (&v)[24]) {
     const uint32_t off = (uint32_t)n * 16u;
     const size_t bb = N * 16;
     if constexpr (P == P64) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) at_mut<double2>(base, c * bb, off) = make_double2(v[2 * c], v[2 * c + 1]);
+        for (int c = 0; c < 12; ++c)
+            st16<NT>(base, c * bb, off, __builtin_bit_cast(uint4, make_double2(v[2 * c], v[2 * c + 1])));
     } else if constexpr (P == P32) {
 #pragma unroll
         for (int b = 0; b < 6; ++b)
-            at_mut<float4>(base, b * bb, off) = make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+            st16<NT>(base, b * bb, off,
+                     __builtin_bit_cast(uint4, make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3])));
     } else {
         float sc = 1.0f;
         if constexpr (P == P16) {
             float m = 0.0f;
 #pragma unroll
             for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
-            nrm[n] = m;
+            if (NT) __builtin_nontemporal_store(m, nrm + n); else nrm[n] = m;
             sc = m > 0.0f ? 1.0f / m : 0.0f;
         }
 #pragma unroll
@@ -142,7 +159,7 @@ __device__ __forceinline__ void st_spinor(void* __restrict__ base, float* __rest
                 else
                     w[q] = f2b(v[8 * b + 2 * q]) | (f2b(v[8 * b + 2 * q + 1]) << 16);
             }
-            at_mut<uint4>(base, b * bb, off) = make_uint4(w[0], w[1], w[2], w[3]);
+            st16<NT>(base, b * bb, off, make_uint4(w[0], w[1], w[2], w[3]));
         }
     }
 }
