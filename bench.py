@@ -110,6 +110,65 @@ def cpu_baseline(pre, seconds=12.0):
                       f"({dt:.1f} s, FP64, OpenMP)"}
 
 
+def trajectory(args):
+    """The 24^3x64, Ls = 24 trajectory workload (c5): a fermion-only EOFA
+    leapfrog trajectory of n_steps x dt from seeded links, pseudofermion and
+    momenta.  Mixed precision (inner solver args.inner) forward, then
+    backward with flipped momenta (reversibility), and the same trajectory
+    with the FP64 solver; reports dH = H_end - H_start for both and the
+    distance between their end points.  Prints one JSON line."""
+    import torch
+    import dwf_inputs as din
+    from paper_1611_00298_amd import Context
+    from paper_1611_00298_amd.hmc import hamiltonian, leapfrog
+
+    pre = din.preset("c5")
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    log("trajectory: generating c5 inputs")
+    U0 = t(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"]))
+    phi = t(din.gaussian_4d(pre["L"], pre["seed_phi"]))
+    P0 = t(din.gaussian_momenta(pre["L"], pre["seed_mom"]))
+    m1, m2, n, dt = pre["m1"], pre["m2"], pre["n_steps"], pre["dt"]
+    ctx = Context(pre["L"], pre["Ls"], U0, M5=pre["M5"], alpha=pre["alpha"])
+    out = {"metric": "fermion-only EOFA trajectory: dH and reversibility, mixed vs FP64 (1 GPU)",
+           "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
+                                  f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}: {n} leapfrog "
+                                  f"steps of dt={dt}, solves to 1e-10", "inner_precision": args.inner},
+           "data": "synthetic (random SU(3) links exp(i eps H), Gaussian pseudofermion and momenta)"}
+    res = {}
+    for label, solver in (("mixed", dict(tol=1e-10, inner=args.inner, reliable_delta=args.delta)),
+                          ("fp64", dict(tol=1e-10, inner="fp64"))):
+        U, P = U0.clone(), P0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+        prog = lambda i, st, lab=label: log(f"trajectory {lab}: force {i}: iters {st['iters']} "
+                                            f"solve {st['seconds']:.2f}s")
+        leapfrog(ctx, U, P, phi, m1, m2, n, dt, progress=prog, **solver)
+        H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        log(f"trajectory {label}: H0 {H0:.6f} H1 {H1:.6f} dH {H1 - H0:.6e} ({sec:.1f} s)")
+        r = {"H0": H0, "dH": H1 - H0, "S0": S0, "S1": S1, "kin0": K0, "kin1": K1, "seconds": sec}
+        if label == "mixed":
+            Ue, Pe = U.clone(), P.clone()
+            P.neg_()
+            leapfrog(ctx, U, P, phi, m1, m2, n, dt, progress=prog, **solver)
+            Hb, _, _, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+            r["reversibility"] = {"max_abs_dU": float((U - U0).abs().max()),
+                                  "max_abs_dP": float((P + P0).abs().max()), "H_back_minus_H0": Hb - H0}
+            log(f"trajectory reversed: |dU| {r['reversibility']['max_abs_dU']:.3e} "
+                f"|dP| {r['reversibility']['max_abs_dP']:.3e}")
+            res["U_mixed"] = Ue
+        else:
+            r["end_point_vs_mixed"] = {"max_abs_dU": float((U - res.pop("U_mixed")).abs().max())}
+        out[label] = r
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +180,9 @@ def main():
     ap.add_argument("--dt", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--trajectory", action="store_true",
+                    help="instead of the step benchmark: the 24^3x64 fermion-only trajectory workload (c5), "
+                         "mixed vs FP64 dH and reversibility")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 x 2 GiB device copies first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -128,6 +190,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
                                    "a design (4D domain decomposition), not implemented"}))
         return 2
+
+    if args.trajectory:
+        return trajectory(args)
 
     import torch
     import dwf_inputs as din
@@ -185,6 +250,14 @@ def main():
     hop_cls = {"fp64": "hop64", "fp32": "hop32", "fp16": "hop16", "bf16": "hopb16"}[args.inner]
     hq = ctx.timing_query(hop_cls)
     h64 = ctx.timing_query("hop64")
+    other = {}
+    for cls, label in (("force", "force (eq. 3.2)"), ("md", "md_update"), ("blas", "CG vector kernels")):
+        q = ctx.timing_query(cls)
+        if q["count"]:
+            gbs = q["bytes"] / (q["ms"] * 1e-3) / 1e9
+            other[cls] = {"kernel": label, "launches": q["count"], "avg_ms": q["ms"] / q["count"],
+                          "avg_bytes": q["bytes"] / q["count"], "achieved_GBs": gbs,
+                          "frac": gbs / HBM_PEAK_GBS}
     ctx.timing_enable(False)
     flops = sum(r["flops"] for r in recs)
     solve_s = [r["seconds"] for r in recs]
@@ -219,6 +292,7 @@ def main():
                                     * pre["Ls"]) / (avg_ms * 1e-3) / 1e9 if hq["count"] else 0.0,
                      "fp64_hop_launches": h64["count"],
                      "fp64_hop_GBs": (h64["bytes"] / (h64["ms"] * 1e-3) / 1e9) if h64["count"] else 0.0},
+        "other_kernels": other,
         "solve": {"mixed_s": sum(solve_s) / len(solve_s), "iters": recs[-1]["iters"],
                   "reliable_updates": recs[-1]["reliable_updates"],
                   "true_resid": recs[-1]["true_resid"]},

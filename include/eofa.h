@@ -144,7 +144,7 @@ int eofa_md_update(eofa_ctx_t *ctx, void *U_dev, void *P_dev, const void *F_dev,
  * eofa_timing_enable(ctx, 1) starts recording (and clears totals);
  * eofa_timing_query synchronises and returns, for kernel class `name`
  * ("hop" = the 5D hopping kernel in any precision, "hop64", "hop32",
- * "hop16", "hopb16", "blas", "force"), the launch count, the summed
+ * "hop16", "hopb16", "blas", "force", "md"), the launch count, the summed
  * duration in ms and the summed algorithmic bytes. */
 int eofa_timing_enable(eofa_ctx_t *ctx, int on);
 int eofa_timing_query(eofa_ctx_t *ctx, const char *name, long *count, double *ms, double *bytes);

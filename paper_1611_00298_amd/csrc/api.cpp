@@ -58,8 +58,9 @@ hipError_t launch_eofa_source(const void* phi, const double* om, void* bLe, void
 int action_blocks(int V);
 hipError_t launch_eofa_action(const void* phi, const void* chiL, const void* chiR, const double* om,
                               double k, void* Mphi, double* partial, int V, int Ls, hipStream_t st);
-hipError_t launch_force(const void* U, const void* chiL, const void* chiR, double k, void* F, void* G,
-                        const int L[4], int Ls, int aperiodic, hipStream_t st);
+hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, const void* chiRe,
+                        const void* chiRo, const int* nbr, const int* sites, double k, void* F, void* G,
+                        const int L[4], int Ls, int aperiodic, int NS, int nblk, size_t N, hipStream_t st);
 int md_blocks(int nlink);
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st);
@@ -94,8 +95,8 @@ struct Half {
     int prec = -1;
 };
 
-enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_NCLS };
-const char* cls_name[C_NCLS] = {"hop64", "hop32", "hop16", "hopb16", "blas", "force"};
+enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_MD, C_NCLS };
+const char* cls_name[C_NCLS] = {"hop64", "hop32", "hop16", "hopb16", "blas", "force", "md"};
 
 struct TimingRec {
     int cls;
@@ -124,6 +125,8 @@ struct eofa_ctx {
     size_t npartial = 0;
     double* sc = nullptr;        // device scalar slots
     double* pinned = nullptr;    // host mirror of the slots
+    double* ring = nullptr;      // pinned [2][4]: per-iteration scalars read one iteration late
+    hipEvent_t ring_ev[2] = {nullptr, nullptr};
     std::map<std::string, Half> ws;
     std::map<std::string, void*> raw;
     // timing
@@ -227,7 +230,7 @@ struct HopCall {
     Half* out = nullptr;
     const Half* aux = nullptr;
     const Half* aux2 = nullptr;
-    Op5 A = I5, B = I5, C = I5;
+    Op5 A = I5, B = I5, C = I5, B2 = I5;
     double ch = 1.0, ca = 1.0, cr = 1.0;
     double mp = 0, mm = 0;
     double* partial = nullptr;
@@ -243,6 +246,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     if (h.hop && h.aux2 && h.A.kind != 0 && h.C.kind != 0) fail(EOFA_EDEVICE, "internal: aux2 with A and C");
     if (!h.hop && h.aux2 && h.C.kind != 0) fail(EOFA_EDEVICE, "internal: aux2 after C");
     if (!h.hop && !h.aux) fail(EOFA_EDEVICE, "internal: local op without input");
+    if (h.B2.kind != 0 && (!h.hop || !h.aux)) fail(EOFA_EDEVICE, "internal: B2 needs a hop with aux");
     HopArgs a;
     memset(&a, 0, sizeof(a));
     a.in = h.in ? h.in->d : nullptr;
@@ -274,6 +278,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.opA = h.A;
     a.opB = h.B;
     a.opC = h.C;
+    a.opB2 = h.B2;
     a.ch = h.ch;
     a.ca = h.ca;
     a.cr = h.cr;
@@ -287,7 +292,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     // bookkeeping: flops (fixed convention) and algorithmic bytes
     double f = 0, nfields = 1;
     if (h.hop) f += 1320.0 + op_flops(h.A), nfields += 1;
-    if (h.aux) f += op_flops(h.B) + (h.hop ? 24.0 : 0.0), nfields += 1;
+    if (h.aux) f += op_flops(h.B) + op_flops(h.B2) + (h.hop ? 24.0 : 0.0), nfields += 1;
     if (h.aux2) f += 24.0, nfields += 1;
     f += op_flops(h.C);
     c->flops += f * (double)c->n5;
@@ -368,6 +373,14 @@ void schur_k2(eofa_ctx* c, int prec, const Half& tmp, const Half& p, Half& out, 
     h.aux = &p; h.B = Mee(c, 0); h.ca = 1.0; h.mp = mp; h.mm = mm; h.partial = partial;
     run_hop(c, h);
 }
+// K2 for a direction kept as pt = Dtilde p:  out_o = M_ee Dtilde^-1 pt_o - Dh_oe tmp_e
+void schur_k2_tilde(eofa_ctx* c, int prec, const Half& tmp, const Half& pt, Half& out, double mp, double mm,
+                    double* partial) {
+    HopCall h;
+    h.prec = prec; h.par = 1; h.in = &tmp; h.out = &out; h.ch = -1.0;
+    h.aux = &pt; h.B = Mee(c, 0); h.B2 = DtInv(c, 0); h.ca = 1.0; h.mp = mp; h.mm = mm; h.partial = partial;
+    run_hop(c, h);
+}
 // K3: tmp_e = M_ee^-dag Dtilde^dag Dh^dag_eo in_o
 void schur_k3(eofa_ctx* c, int prec, const Half& in, Half& tmp, double mp, double mm) {
     HopCall h;
@@ -395,6 +408,18 @@ void schur_k4_update(eofa_ctx* c, int prec, const Half& tmp, const Half& w, Half
     h.partial = partial;
     h.dev_alpha = true; h.s_num = s_num; h.s_den = s_den; h.s_alpha = s_alpha;
     run_hop(c, h);
+}
+
+// p <- z + beta p_old (or p <- z), pt <- Dtilde p; beta = sc[i_new] / sc[i_old]
+// (pt == nullptr: p <- Dtilde z + beta p, the direction kept in Cayley form)
+void pupdate(eofa_ctx* c, int prec, const Half& z, const Half* pold, Half& p, Half* pt, int i_new, int i_old,
+             double mp, double mm) {
+    const int ev = timing_begin(c);
+    hipchk(launch_pupdate(prec, z.d, z.nrm, pold ? pold->d : nullptr, pold ? pold->nrm : nullptr, p.d, p.nrm,
+                          pt ? pt->d : nullptr, pt ? pt->nrm : nullptr, c->sc, i_new, i_old, pold ? 0 : 1, c->Vh,
+                          c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, c->nblk_hop, c->st),
+           "pupdate");
+    timing_end(c, ev, C_BLAS, (double)c->n5 * ((pold ? 3.0 : 2.0) + (pt ? 1.0 : 0.0)) * spinor_bytes(prec));
 }
 
 void check_finite(double v, const char* what) {
@@ -446,7 +471,7 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
     Half& z = ws(c, "z", prec);
     Half* pr[XBATCH];   // ring of search directions p_k (buffer k mod XBATCH)
     for (int j = 0; j < XBATCH; ++j) pr[j] = &ws(c, "p" + std::to_string(j), prec);
-    Half& pt = ws(c, "pt", prec);
+    Half* ptp = mixed ? nullptr : &ws(c, "pt", prec);   // Dtilde p (FP64 path)
     Half& w = ws(c, "w", prec);
     Half& tmp = ws(c, "tmp_lo_e", prec);
     Half& xl = mixed ? ws(c, "x_lo", px) : x;
@@ -476,46 +501,66 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
         pending0 = k + 1;
     };
     int cur = S_ZZ0, nxt = S_ZZ1;
-    // z = Mhat^dag r ; p_0 = z ; pt = Dtilde p_0
+    // z = Mhat^dag r ; p_0 = z ; pt = Dtilde p_0 (mixed: the ring holds Dtilde p)
     schur_k3(c, prec, r, tmp, mp, mm);
     schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
     reduce(c, nb, cur);
-    hipchk(launch_pupdate(prec, z.d, z.nrm, nullptr, nullptr, pr[0]->d, pr[0]->nrm, pt.d, pt.nrm, c->sc, cur,
-                          cur, 1, c->Vh, c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+    pupdate(c, prec, z, nullptr, *pr[0], ptp, cur, cur, mp, mm);
     double rmax = std::sqrt(rr);
     int k = 0;
     if (mixed) {
+        // The search directions are kept in Cayley form, pt_k = Dtilde p_k:
+        // K1 reads pt_k, K2 forms M_ee p_k = M_ee Dtilde^-1 pt_k in its
+        // epilogue, and x_lo accumulates Dtilde x (undone before each
+        // reliable update), which saves writing p next to pt.
+        auto fold_x = [&]() {
+            local_op(c, px, xl, xl, I5, DtInv(c, 0), mp, mm);
+            hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+        };
         // Low-precision iterations keep z = Mhat^dag r by its own recursion
         // z <- z - alpha Mhat^dag w (folded into K4, so r is not stored);
         // |r|^2 follows |r_{k+1}|^2 = |r_k|^2 - alpha |z_k|^2 (exact in exact
         // arithmetic, since (r_k, Mhat p_k) = (z_k, p_k) = |z_k|^2).  Reliable
         // updates replace the estimate by the FP64 true residual and z by
         // Mhat^dag of it; convergence is only declared on a true residual.
+        // The scalars of iteration k are copied to the host ring after its K4
+        // and read while iteration k+1 runs, so the host never waits on an
+        // idle GPU; decisions therefore use the estimate one iteration late.
         double rr_est = rr;
+        int pend_cur = -1;          // slot of |z_k|^2 of the pending ring entry, -1: none
         while (res.iters < maxiter) {
             Half& p = *pr[k % XBATCH];
-            schur_k1(c, prec, pt, tmp, mp, mm);
-            schur_k2(c, prec, tmp, p, w, mp, mm, c->partial);
+            schur_k1(c, prec, p, tmp, mp, mm);
+            schur_k2_tilde(c, prec, tmp, p, w, mp, mm, c->partial);
             reduce(c, nb, S_WW);
             schur_k3(c, prec, w, tmp, mp, mm);
             schur_k4_update(c, prec, tmp, w, z, mp, mm, cur, S_WW, S_ALPHA + k % XBATCH, c->partial);
             reduce(c, nb, nxt);
             res.iters++;
-            const double* sv = read_slots(c, S_WW, 3);
-            const double ww = sv[S_WW - S_WW], zz = sv[cur - S_WW];
-            check_finite(ww, "|Mhat p|^2");
-            check_finite(sv[nxt - S_WW], "|z|^2");
-            rr_est -= zz / ww * zz;
+            double* slot_k = c->ring + 4 * (k & 1);
+            hipchk(hipMemcpyAsync(slot_k, c->sc + S_WW, sizeof(double) * 3, hipMemcpyDeviceToHost, c->st),
+                   "hipMemcpy(scalars)");
+            hipchk(hipEventRecord(c->ring_ev[k & 1], c->st), "hipEventRecord");
+            if (pend_cur >= 0) {   // iteration k-1
+                hipchk(hipEventSynchronize(c->ring_ev[(k - 1) & 1]), "hipEventSynchronize");
+                const double* sv = c->ring + 4 * ((k - 1) & 1);
+                const double ww = sv[0], zz = sv[pend_cur - S_WW], zn = sv[(pend_cur == S_ZZ0 ? S_ZZ1 : S_ZZ0) - S_WW];
+                check_finite(ww, "|Mhat p|^2");
+                check_finite(zn, "|z|^2");
+                rr_est -= zz / ww * zz;
+            }
+            pend_cur = cur;
             const double rn = std::sqrt(std::max(rr_est, 0.0));
             if (rn <= delta * rmax || rn <= thresh) {
                 // reliable update: fold the directions into x_lo, x_lo into x, recompute r in FP64
                 flush(k);
-                hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+                fold_x();
                 rr = true_residual();
                 check_finite(rr, "true residual");
                 res.reliable++;
                 rmax = std::sqrt(rr);
                 rr_est = rr;
+                pend_cur = -1;   // the true residual includes iteration k
                 if (rmax <= thresh) { res.converged = true; break; }
                 convert(c, r64, r);
                 schur_k3(c, prec, r, tmp, mp, mm);
@@ -525,17 +570,16 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
             if (k - pending0 + 1 == XBATCH) flush(k);
             if (res.iters >= maxiter) { flush(k); break; }
             Half& pn1 = *pr[(k + 1) % XBATCH];
-            hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pn1.d, pn1.nrm, pt.d, pt.nrm, c->sc, nxt, cur, 0,
-                                  c->Vh, c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+            pupdate(c, prec, z, &p, pn1, nullptr, nxt, cur, mp, mm);
             c->flops += 72.0 * (double)c->n5 + 48.0 * (double)c->n5;
             std::swap(cur, nxt);
             ++k;
         }
-        if (!res.converged)
-            hipchk(launch_accum_hi(px, x.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+        if (!res.converged) fold_x();
         return res;
     }
     // FP64: plain CGNR with the recursively updated residual r
+    Half& pt = *ptp;
     while (res.iters < maxiter) {
         Half& p = *pr[k % XBATCH];
         // w = Mhat p, |w|^2
@@ -566,8 +610,7 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
         schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
         reduce(c, nb, nxt);
         Half& pn1 = *pr[(k + 1) % XBATCH];
-        hipchk(launch_pupdate(prec, z.d, z.nrm, p.d, p.nrm, pn1.d, pn1.nrm, pt.d, pt.nrm, c->sc, nxt, cur, 0,
-                              c->Vh, c->Ls, c->NS, c->N, c->b5, c->c5, mp, mm, nb, c->st), "pupdate");
+        pupdate(c, prec, z, &p, pn1, &pt, nxt, cur, mp, mm);
         c->flops += 72.0 * (double)c->n5 + 48.0 * (double)c->n5;
         std::swap(cur, nxt);
         ++k;
@@ -747,6 +790,8 @@ void free_ctx(eofa_ctx* c) {
     if (c->partial) hipFree(c->partial);
     if (c->sc) hipFree(c->sc);
     if (c->pinned) hipHostFree(c->pinned);
+    if (c->ring) hipHostFree(c->ring);
+    for (auto e : c->ring_ev) if (e) hipEventDestroy(e);
     for (auto e : c->evpool) hipEventDestroy(e);
     delete c;
 }
@@ -903,6 +948,8 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             hipchk(hipMalloc((void**)&c->sc, sizeof(double) * S_NSLOT), "hipMalloc(scalars)");
             hipchk(hipMemsetAsync(c->sc, 0, sizeof(double) * S_NSLOT, c->st), "hipMemset");
             hipchk(hipHostMalloc((void**)&c->pinned, sizeof(double) * S_NSLOT, 0), "hipHostMalloc");
+            hipchk(hipHostMalloc((void**)&c->ring, sizeof(double) * 8, 0), "hipHostMalloc");
+            for (auto& e : c->ring_ev) hipchk(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
             hipchk(hipMalloc((void**)&c->nbr, sizeof(int) * 2 * 8 * c->Vh), "hipMalloc(nbr)");
             hipchk(hipMalloc(&c->gauge[P64], (size_t)2 * 8 * 9 * c->Vh * 16), "hipMalloc(gauge)");
             hipchk(hipMalloc(&c->U_nat, (size_t)4 * c->V * 9 * 16), "hipMalloc(U)");
@@ -1028,10 +1075,18 @@ int eofa_force(eofa_ctx_t* c, double m1, double m2, const void* phi, const void*
             chiL = cl;
             chiR = cr;
         }
+        // chi into the FP64 device layout, then one work-item per 5D site
+        Half& le = ws(c, "force_chiL_e", P64);
+        Half& lo = ws(c, "force_chiL_o", P64);
+        Half& re = ws(c, "force_chiR_e", P64);
+        Half& ro = ws(c, "force_chiR_o", P64);
+        hipchk(launch_nat5_to_dev(chiL, le.d, lo.d, c->L, c->Ls, c->N, c->st), "layout");
+        hipchk(launch_nat5_to_dev(chiR, re.d, ro.d, c->L, c->Ls, c->N, c->st), "layout");
         const int ev = timing_begin(c);
-        hipchk(launch_force(c->U_nat, chiL, chiR, k, F, G, c->L, c->Ls, c->aperiodic, c->st), "force");
-        timing_end(c, ev, C_FORCE,
-                   4.0 * c->V * c->Ls * 192.0 + 4.0 * c->V * 144.0 * (G ? 3.0 : 2.0));
+        hipchk(launch_force(c->U_nat, le.d, lo.d, re.d, ro.d, c->nbr, c->sites[P64], k, F, G, c->L, c->Ls,
+                            c->aperiodic, c->NS, c->nblk_hop, c->N, c->st), "force");
+        // algorithmic bytes: chi_L and chi_R once, U, F (and G)
+        timing_end(c, ev, C_FORCE, 2.0 * c->V * c->Ls * 192.0 + 4.0 * c->V * 144.0 * (G ? 3.0 : 2.0));
         hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
         return status;
     });
@@ -1042,7 +1097,11 @@ int eofa_md_update(eofa_ctx_t* c, void* U, void* P, const void* F, double dt_p, 
     return guarded([&]() -> int {
         if (!c || !U || !P) fail(EOFA_EINVAL, "NULL argument");
         const int nlink = 4 * c->V;
+        const int ev = timing_begin(c);
         hipchk(launch_md_update(U, P, F, dt_p, dt_u, nlink, kin ? c->partial : nullptr, c->st), "md update");
+        // algorithmic bytes: P (and F) read, P written; U read and written when dt_u != 0
+        const bool pf = F && dt_p != 0.0, uu = dt_u != 0.0;
+        timing_end(c, ev, C_MD, (double)nlink * 144.0 * ((pf ? 3.0 : 1.0) + (uu ? 2.0 : 0.0)));
         if (kin) {
             reduce(c, md_blocks(nlink), S_T1);
             *kin = read_slot(c, S_T1);

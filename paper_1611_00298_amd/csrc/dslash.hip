@@ -623,7 +623,11 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
                 for (int k = 0; k < 24; ++k) x[k] = 0;
             }
             const A ca = (A)(a.ca * alpha);
-            if (a.opB.kind == 1) {
+            if (a.opB2.kind != 0) {
+                column_phase(lds, tid, sl, s, Ls, x, a.opB, ca, a.opB2, mp, mm);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] += x[k];
+            } else if (a.opB.kind == 1) {
                 put_row(lds, tid, x);
                 __syncthreads();
                 A bx[24];
@@ -679,7 +683,8 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
 // ---------------------------------------------------------------------------
 // CG search-direction update with the Cayley factor needed by the next
 // Schur application:  p <- z + beta p  (beta = sc[i1]/sc[i0], or p <- z on
-// the first call), pt <- Dtilde p = (b5 + c5 L) p.
+// the first call), pt <- Dtilde p = (b5 + c5 L) p.  With pt == nullptr only
+// the Cayley-transformed direction is kept: p <- Dtilde z + beta p.
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_nrm, const void* pold,
@@ -701,6 +706,25 @@ __global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_n
     A v[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = 0;
+    if (!pt) {
+        // search directions kept as pt = Dtilde p:  pt <- Dtilde z + beta pt_old
+        if (active) ld_spinor<P>(z, z_nrm, N, n, v);
+        put_row(lds, tid, v);
+        __syncthreads();
+        A t[24];
+        row_bidiag(lds, tid, s, Ls, v, t, (A)b5, (A)c5, 0, (A)mp_, (A)mm_);
+        if (active) {
+            if (!first) {
+                const A beta = (A)(sc[i_new] / sc[i_old]);
+                A q[24];
+                ld_spinor<P>(pold, pold_nrm, N, n, q);
+#pragma unroll
+                for (int k = 0; k < 24; ++k) t[k] = fmadd(beta, q[k], t[k]);
+            }
+            st_spinor<P>(p, p_nrm, N, n, t);
+        }
+        return;
+    }
     if (active) {
         ld_spinor<P>(z, z_nrm, N, n, v);
         if (!first) {
@@ -726,7 +750,7 @@ template <int P, bool DAG, bool HOP>
 static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     using A = typename PT<P>::A;
     const int NT = a.NS * a.Ls;
-    const bool need_lds = HOP ? (a.opA.kind != 0 || a.opC.kind != 0 || (a.aux && a.opB.kind != 0))
+    const bool need_lds = HOP ? (a.opA.kind != 0 || a.opC.kind != 0 || (a.aux && (a.opB.kind != 0 || a.opB2.kind != 0)))
                               : (a.opB.kind != 0 || a.opC.kind != 0);
     const size_t tile = need_lds ? (size_t)STR * NT * sizeof(A) : 0;
     if constexpr (P == P16 && HOP) {

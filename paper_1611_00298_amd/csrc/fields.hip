@@ -6,29 +6,6 @@
 
 namespace eofa {
 
-struct Geo {
-    int L[4];
-    int V, Vh, Ls;
-    int aperiodic;
-};
-
-// natural site index of checkerboard index cb with parity p
-__device__ __forceinline__ int natural_site(const Geo& g, int p, int cb, int c[4]) {
-    const int i0 = 2 * cb;
-    int x0 = i0 % g.L[0];
-    int rem = i0 / g.L[0];
-    c[1] = rem % g.L[1];
-    rem /= g.L[1];
-    c[2] = rem % g.L[2];
-    c[3] = rem / g.L[2];
-    c[0] = x0 + ((p + c[1] + c[2] + c[3]) & 1);
-    return i0 + (c[0] - x0);
-}
-
-__device__ __forceinline__ int index4(const Geo& g, const int c[4]) {
-    return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
-}
-
 // Links of both output parities with -1/2 and the boundary sign folded in,
 // and the neighbour table.  One work-item per (parity, cb).
 __global__ void k_ingest_gauge(const double2* __restrict__ U, double2* __restrict__ G,

@@ -9,7 +9,7 @@
 // boundary sign of the link.  Because (1+gamma_mu) has rank two,
 // B = sum_{s} sum_{j=0,1} h_j (x) g_j^dag with h = chi_up + A_mu chi_lo at x
 // and g = chi_up - A_mu chi_lo at (x+mu, Ls-1-s) (the minus sign is gamma_5).
-// FP64 throughout; one work-item per link, fields in the natural layout.
+// FP64 throughout; one work-item per 5D site, fields in the FP64 device layout.
 #include "internal.h"
 
 namespace eofa {
@@ -30,64 +30,20 @@ __device__ __forceinline__ void amul(int mu, cplx v2, cplx v3, cplx& o0, cplx& o
     }
 }
 
-__global__ void __launch_bounds__(256) k_force(const double2* __restrict__ U,
-                                               const double2* __restrict__ chiL,
-                                               const double2* __restrict__ chiR, double k,
-                                               double2* __restrict__ F, double2* __restrict__ G,
-                                               int Lx, int Ly, int Lz, int Lt, int Ls, int aperiodic) {
-    const int V = Lx * Ly * Lz * Lt;
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= 4 * V) return;
-    const int mu = l / V, i = l - mu * V;
-    int c[4] = {i % Lx, (i / Lx) % Ly, (i / (Lx * Ly)) % Lz, i / (Lx * Ly * Lz)};
-    const int L[4] = {Lx, Ly, Lz, Lt};
-    double sigma = 1.0;
-    c[mu] += 1;
-    if (c[mu] == L[mu]) { c[mu] = 0; if (mu == 3 && aperiodic) sigma = -1.0; }
-    const int j = c[0] + Lx * (c[1] + Ly * (c[2] + Lz * c[3]));
-
-    cplx B[9];
-    for (int q = 0; q < 9; ++q) B[q] = {0.0, 0.0};
-    for (int sys = 0; sys < 2; ++sys) {
-        const double2* chi = sys ? chiR : chiL;
-        const double sg = sys ? -1.0 : 1.0;
-        for (int s = 0; s < Ls; ++s) {
-            const double2* a = chi + ((size_t)s * V + i) * 12;
-            const double2* b = chi + ((size_t)(Ls - 1 - s) * V + j) * 12;
-            cplx h[2][3], g[2][3];
-            for (int cc = 0; cc < 3; ++cc) {
-                cplx a0 = {a[cc].x, a[cc].y}, a1 = {a[3 + cc].x, a[3 + cc].y};
-                cplx a2 = {a[6 + cc].x, a[6 + cc].y}, a3 = {a[9 + cc].x, a[9 + cc].y};
-                cplx b0 = {b[cc].x, b[cc].y}, b1 = {b[3 + cc].x, b[3 + cc].y};
-                cplx b2 = {b[6 + cc].x, b[6 + cc].y}, b3 = {b[9 + cc].x, b[9 + cc].y};
-                cplx p0, p1, q0, q1;
-                amul(mu, a2, a3, p0, p1);
-                amul(mu, b2, b3, q0, q1);
-                h[0][cc] = {a0.r + p0.r, a0.i + p0.i};
-                h[1][cc] = {a1.r + p1.r, a1.i + p1.i};
-                g[0][cc] = {b0.r - q0.r, b0.i - q0.i};
-                g[1][cc] = {b1.r - q1.r, b1.i - q1.i};
-            }
-            for (int jj = 0; jj < 2; ++jj)
-                for (int x = 0; x < 3; ++x)
-                    for (int y = 0; y < 3; ++y) {
-                        cplx t = cmulc(h[jj][x], g[jj][y]);
-                        B[3 * x + y].r += sg * t.r;
-                        B[3 * x + y].i += sg * t.i;
-                    }
-        }
-    }
-    const double2* Ul = U + ((size_t)mu * V + i) * 9;
+// F and G of one link from B = B[chi_L] - B[chi_R] and the link U (natural
+// layout entries, row major), sigma the boundary sign of the link:
+//   W = sigma k (U B^dag - B U^dag),  F = 1/4 TA(-i W),  G = -sigma k B.
+__device__ __forceinline__ void force_from_B(const cplx (&B)[9], const double2* __restrict__ Ul, double sigma, double k,
+                             double2* __restrict__ Fl, double2* __restrict__ Gl) {
     cplx u[9];
     for (int q = 0; q < 9; ++q) u[q] = {Ul[q].x, Ul[q].y};
-    // W = sigma k (U B^dag - B U^dag);  Y = -i W
-    cplx Y[9];
+    cplx Y[9];   // Y = -i W
     for (int x = 0; x < 3; ++x)
         for (int y = 0; y < 3; ++y) {
             cplx w = {0.0, 0.0};
             for (int q = 0; q < 3; ++q) {
-                cplx t1 = cmulc(u[3 * x + q], B[3 * y + q]);   // U_xq conj(B_yq)
-                cplx t2 = cmulc(B[3 * x + q], u[3 * y + q]);   // B_xq conj(U_yq)
+                const cplx t1 = cmulc(u[3 * x + q], B[3 * y + q]);   // U_xq conj(B_yq)
+                const cplx t2 = cmulc(B[3 * x + q], u[3 * y + q]);   // B_xq conj(U_yq)
                 w.r += t1.r - t2.r;
                 w.i += t1.i - t2.i;
             }
@@ -97,7 +53,6 @@ __global__ void __launch_bounds__(256) k_force(const double2* __restrict__ U,
         }
     // F = 1/4 [ (Y + Y^dag)/2 - tr(Y + Y^dag)/6 ]
     const double tr = (Y[0].r + Y[4].r + Y[8].r) / 3.0;
-    double2* Fl = F + ((size_t)mu * V + i) * 9;
     for (int x = 0; x < 3; ++x)
         for (int y = 0; y < 3; ++y) {
             const cplx a = Y[3 * x + y], b = Y[3 * y + x];
@@ -105,10 +60,103 @@ __global__ void __launch_bounds__(256) k_force(const double2* __restrict__ U,
             if (x == y) re -= tr;
             Fl[3 * x + y] = make_double2(0.25 * re, 0.25 * im);
         }
-    if (G) {
-        double2* Gl = G + ((size_t)mu * V + i) * 9;
+    if (Gl) {
         const double f = -sigma * k;
         for (int q = 0; q < 9; ++q) Gl[q] = make_double2(f * B[q].r, f * B[q].i);
+    }
+}
+
+// Work-item (site, s) of parity p = blockIdx.y, workgroups of NS whole sites
+// x Ls slices in the traversal of the FP64 hop (site table, XCD ranges).
+// chi_L, chi_R in the FP64 device layout (block c of 5D site n at
+// base[c N + n], n = cb Ls + s).  For each direction mu every work-item forms
+// its slice's term of B_mu(x) = sum_{s, j} h_j(x, s) (x) g_j(x+mu, Ls-1-s)^dag
+// for chi_L minus chi_R; the Ls terms of a site are summed in LDS in a fixed
+// order, and 4 NS work-items then finish the links of the workgroup's sites.
+__global__ void __launch_bounds__(256, 3) k_force_dev(const double2* __restrict__ chiLe,
+                                                   const double2* __restrict__ chiLo,
+                                                   const double2* __restrict__ chiRe,
+                                                   const double2* __restrict__ chiRo,
+                                                   const double2* __restrict__ U, const int* __restrict__ nbr,
+                                                   const int* __restrict__ sites, double k,
+                                                   double2* __restrict__ F, double2* __restrict__ G, Geo g,
+                                                   int NS, size_t N) {
+    extern __shared__ double red[];   // [NT][19] slice terms, then [4][NS][18] sums
+    const int NT = blockDim.x, tid = threadIdx.x, Ls = g.Ls;
+    const int p = blockIdx.y;
+    const int sl = tid / Ls, s = tid - sl * Ls;
+    const int lb = xcd_block(gridDim.x);
+    const int slot = lb * NS + sl;
+    const int cb = sites ? sites[slot] : slot;
+    const bool active = cb < g.Vh;
+    const double2* ownL = p ? chiLo : chiLe;
+    const double2* othL = p ? chiLe : chiLo;
+    const double2* ownR = p ? chiRo : chiRe;
+    const double2* othR = p ? chiRe : chiRo;
+    double* sums = red + (size_t)NT * 19;
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        cplx acc[9];
+        for (int q = 0; q < 9; ++q) acc[q] = {0.0, 0.0};
+        if (active) {
+            const int nb = nbr[((size_t)p * 8 + mu) * g.Vh + cb];
+            const size_t na = (size_t)cb * Ls + s, nn = (size_t)nb * Ls + (Ls - 1 - s);
+#pragma unroll 1
+            for (int sys = 0; sys < 2; ++sys) {
+                const double2* a = sys ? ownR : ownL;
+                const double2* b = sys ? othR : othL;
+                const double sg = sys ? -1.0 : 1.0;
+                cplx h[2][3], gg[2][3];
+                for (int cc = 0; cc < 3; ++cc) {
+                    const double2 a0 = a[cc * N + na], a1 = a[(3 + cc) * N + na];
+                    const double2 a2 = a[(6 + cc) * N + na], a3 = a[(9 + cc) * N + na];
+                    const double2 b0 = b[cc * N + nn], b1 = b[(3 + cc) * N + nn];
+                    const double2 b2 = b[(6 + cc) * N + nn], b3 = b[(9 + cc) * N + nn];
+                    cplx p0, p1, q0, q1;
+                    amul(mu, {a2.x, a2.y}, {a3.x, a3.y}, p0, p1);
+                    amul(mu, {b2.x, b2.y}, {b3.x, b3.y}, q0, q1);
+                    h[0][cc] = {a0.x + p0.r, a0.y + p0.i};
+                    h[1][cc] = {a1.x + p1.r, a1.y + p1.i};
+                    gg[0][cc] = {b0.x - q0.r, b0.y - q0.i};
+                    gg[1][cc] = {b1.x - q1.r, b1.y - q1.i};
+                }
+                for (int j = 0; j < 2; ++j)
+                    for (int x = 0; x < 3; ++x)
+                        for (int y = 0; y < 3; ++y) {
+                            const cplx t = cmulc(h[j][x], gg[j][y]);
+                            acc[3 * x + y].r += sg * t.r;
+                            acc[3 * x + y].i += sg * t.i;
+                        }
+            }
+        }
+        for (int q = 0; q < 9; ++q) {
+            red[tid * 19 + 2 * q] = acc[q].r;
+            red[tid * 19 + 2 * q + 1] = acc[q].i;
+        }
+        __syncthreads();
+        // sum over s in a fixed order: sums[mu][site][18]
+        for (int t = tid; t < NS * 18; t += NT) {
+            const int j = t / 18, q = t - 18 * j;
+            double v = 0;
+            for (int u = 0; u < Ls; ++u) v += red[(j * Ls + u) * 19 + q];
+            sums[mu * NS * 18 + t] = v;
+        }
+        __syncthreads();
+    }
+    // one work-item per (site, mu) finishes the links
+    for (int t = tid; t < 4 * NS; t += NT) {
+        const int mu = t / NS, j = t - mu * NS;
+        const int slot2 = lb * NS + j;
+        const int cb2 = sites ? sites[slot2] : slot2;
+        if (cb2 >= g.Vh) continue;
+        int c[4];
+        const int i = natural_site(g, p, cb2, c);
+        const double sigma = (mu == 3 && g.aperiodic && c[3] == g.L[3] - 1) ? -1.0 : 1.0;
+        cplx B[9];
+        const double* bs = sums + (mu * NS + j) * 18;
+        for (int q = 0; q < 9; ++q) B[q] = {bs[2 * q], bs[2 * q + 1]};
+        const size_t l = ((size_t)mu * g.V + i) * 9;
+        force_from_B(B, U + l, sigma, k, F + l, G ? G + l : nullptr);
     }
 }
 
@@ -187,13 +235,20 @@ __global__ void __launch_bounds__(256) k_md_update(double2* __restrict__ U, doub
     }
 }
 
-hipError_t launch_force(const void* U, const void* chiL, const void* chiR, double k, void* F, void* G,
-                        const int L[4], int Ls, int aperiodic, hipStream_t st) {
-    const int V = L[0] * L[1] * L[2] * L[3];
-    const int n = 4 * V;
-    hipLaunchKernelGGL(k_force, dim3((n + 255) / 256), dim3(256), 0, st, (const double2*)U,
-                       (const double2*)chiL, (const double2*)chiR, k, (double2*)F, (double2*)G,
-                       L[0], L[1], L[2], L[3], Ls, aperiodic);
+hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, const void* chiRe,
+                        const void* chiRo, const int* nbr, const int* sites, double k, void* F, void* G,
+                        const int L[4], int Ls, int aperiodic, int NS, int nblk, size_t N, hipStream_t st) {
+    Geo g;
+    for (int mu = 0; mu < 4; ++mu) g.L[mu] = L[mu];
+    g.V = L[0] * L[1] * L[2] * L[3];
+    g.Vh = g.V / 2;
+    g.Ls = Ls;
+    g.aperiodic = aperiodic;
+    const int NT = NS * Ls;
+    const size_t shm = sizeof(double) * ((size_t)NT * 19 + (size_t)4 * NS * 18);
+    hipLaunchKernelGGL(k_force_dev, dim3(nblk, 2), dim3(NT), shm, st, (const double2*)chiLe,
+                       (const double2*)chiLo, (const double2*)chiRe, (const double2*)chiRo, (const double2*)U,
+                       nbr, sites, k, (double2*)F, (double2*)G, g, NS, N);
     return hipGetLastError();
 }
 

@@ -233,6 +233,33 @@ __device__ __forceinline__ int xcd_block(int nblk) {
 }
 
 // ---------------------------------------------------------------------------
+// lattice geometry: natural index i = x + Lx*(y + Ly*(z + Lz*t)),
+// checkerboard index cb = i/2 within parity p = (x+y+z+t) mod 2
+// ---------------------------------------------------------------------------
+struct Geo {
+    int L[4];
+    int V, Vh, Ls;
+    int aperiodic;
+};
+
+// natural site index of checkerboard index cb with parity p
+__device__ __forceinline__ int natural_site(const Geo& g, int p, int cb, int c[4]) {
+    const int i0 = 2 * cb;
+    int x0 = i0 % g.L[0];
+    int rem = i0 / g.L[0];
+    c[1] = rem % g.L[1];
+    rem /= g.L[1];
+    c[2] = rem % g.L[2];
+    c[3] = rem / g.L[2];
+    c[0] = x0 + ((p + c[1] + c[2] + c[3]) & 1);
+    return i0 + (c[0] - x0);
+}
+
+__device__ __forceinline__ int index4(const Geo& g, const int c[4]) {
+    return c[0] + g.L[0] * (c[1] + g.L[1] * (c[2] + g.L[2] * c[3]));
+}
+
+// ---------------------------------------------------------------------------
 // kernel arguments
 // ---------------------------------------------------------------------------
 
@@ -245,9 +272,9 @@ struct Op5 {
     double a, b;
 };
 
-// out = C( ch * A(Dh in) + ca * B(aux) + cr * aux2 ), and optionally the
-// per-workgroup partial sums of |out|^2.  A and C act through LDS; B is a
-// bidiagonal (or identity) op read directly from aux.
+// out = C( ch * A(Dh in) + ca * B2(B(aux)) + cr * aux2 ), and optionally the
+// per-workgroup partial sums of |out|^2.  A, C and B2 act through LDS column
+// sweeps; B alone (B2 = 1) is a bidiagonal or identity op by row exchange.
 struct HopArgs {
     const void* in; const float* in_nrm;
     void* out; float* out_nrm;
@@ -262,6 +289,7 @@ struct HopArgs {
     size_t N;
     double mp, mm;
     Op5 opA, opB, opC;
+    Op5 opB2;            // if non-trivial, aux goes through a column sweep: ca B2(B(aux))
     double ch, ca, cr;
     double* partial;
     // optional device scalar: ch and ca are multiplied by alpha =

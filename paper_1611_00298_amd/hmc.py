@@ -16,14 +16,17 @@ def hamiltonian(ctx: Context, U, P, phi, m1, m2, **solver):
     return kin + S, S, kin, st
 
 
-def leapfrog(ctx: Context, U, P, phi, m1, m2, n_steps, dt, **solver):
-    """In-place leapfrog trajectory; returns per-step statistics."""
+def leapfrog(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, **solver):
+    """In-place leapfrog trajectory; returns per-step statistics.
+    progress(i, stats), if given, is called after force evaluation i."""
     stats = []
 
     def force():
         ctx.update_gauge(U)
         F, _, st = ctx.eofa_force(m1, m2, phi=phi, **solver)
         stats.append(st)
+        if progress is not None:
+            progress(len(stats) - 1, st)
         return F
 
     F = force()
