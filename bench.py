@@ -85,6 +85,26 @@ def copy_calibration(dev):
     del x, y
 
 
+def elementwise_reference(dev):
+    """Best of 3 timed 2 GiB elementwise kernels (y = 1 * x): the HBM rate
+    a plain streaming kernel reaches on this GPU (read + write bytes / time)."""
+    import torch
+    x = torch.ones(512 * 1024 * 1024, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.mul(x, 1.0, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    return 2 * 2 * 1024**3 / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(pre, seconds=12.0):
     """The oracle's D_DWF on a slab of the workload's lattice (all of
     Lx, Ly, Lz and Ls, first 4 time slices), repeated for ~`seconds`."""
@@ -247,6 +267,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
+    ref_gbs = elementwise_reference(dev)
     hop_cls = {"fp64": "hop64", "fp32": "hop32", "fp16": "hop16", "bf16": "hopb16"}[args.inner]
     hq = ctx.timing_query(hop_cls)
     h64 = ctx.timing_query("hop64")
@@ -286,6 +307,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.inner, args.workload),
+                     "elementwise_ref_GBs": ref_gbs, "frac_of_elementwise_ref": achieved / ref_gbs,
                      "kernel": f"k_hop<{args.inner}> (5D hopping + fused 5D ops)",
                      "launches": hq["count"], "avg_ms": avg_ms, "avg_bytes": avg_bytes,
                      "hop_gflops": (1320 * pre["L"][0] * pre["L"][1] * pre["L"][2] * pre["L"][3] // 2

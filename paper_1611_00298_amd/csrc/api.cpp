@@ -856,12 +856,12 @@ std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
 }
 
 // Default tiling per precision (measured at 24^3x64, Ls = 24, and in a
-// model of the per-XCD L2): slabs along z, tiles of 4 y rows by the slab's
-// z planes, walked along t.  The tuning override EOFA_TILE="split,ty,tz,tt,sweep"
-// with dims given as y, z or t replaces it (e.g. "z,4,3,1,t").
+// model of the per-XCD L2): slabs along z, tiles of 4 (FP16) or 8 (other
+// precisions) y rows by the slab's z planes, walked along t.  The tuning
+// override EOFA_TILE="split,ty,tz,tt,sweep" with dims given as y, z or t
+// replaces it (e.g. "z,4,3,1,t").
 Tiling default_tiling(const eofa_ctx* c, int prec) {
-    (void)prec;
-    Tiling T{0, 3, {4, 1, 1}};
+    Tiling T{0, 3, {prec == P16 ? 4 : 8, 1, 1}};
     if (c->L[2] % 8 == 0) { T.split = 2; T.ext[1] = c->L[2] / 8; }
     else if (c->L[3] % 8 == 0) { T.split = 3; T.sweep = 3; T.ext[0] = 6; T.ext[1] = 4; }
     else if (c->L[1] % 8 == 0) { T.split = 1; T.ext[0] = c->L[1] / 8; T.ext[1] = c->L[2]; }

@@ -69,10 +69,11 @@ __device__ __forceinline__ void force_from_B(const cplx (&B)[9], const double2* 
 // Work-item (site, s) of parity p = blockIdx.y, workgroups of NS whole sites
 // x Ls slices in the traversal of the FP64 hop (site table, XCD ranges).
 // chi_L, chi_R in the FP64 device layout (block c of 5D site n at
-// base[c N + n], n = cb Ls + s).  For each direction mu every work-item forms
-// its slice's term of B_mu(x) = sum_{s, j} h_j(x, s) (x) g_j(x+mu, Ls-1-s)^dag
-// for chi_L minus chi_R; the Ls terms of a site are summed in LDS in a fixed
-// order, and 4 NS work-items then finish the links of the workgroup's sites.
+// base[c N + n], n = cb Ls + s).  For each system and direction mu every
+// work-item forms its slice's term of
+// B_mu(x) = sum_{s, j} h_j(x, s) (x) g_j(x+mu, Ls-1-s)^dag; the Ls terms of a
+// site are summed in LDS in a fixed order (chi_R's sums subtracted from
+// chi_L's), and 4 NS work-items then finish the links of the workgroup's sites.
 __global__ void __launch_bounds__(256, 3) k_force_dev(const double2* __restrict__ chiLe,
                                                    const double2* __restrict__ chiLo,
                                                    const double2* __restrict__ chiRe,
@@ -94,29 +95,31 @@ __global__ void __launch_bounds__(256, 3) k_force_dev(const double2* __restrict_
     const double2* ownR = p ? chiRo : chiRe;
     const double2* othR = p ? chiRe : chiRo;
     double* sums = red + (size_t)NT * 19;
+    const size_t na = (size_t)cb * Ls + s;
+    // chi_L then chi_R: the work-item's own spinor is loaded once per system
+    // and kept in registers over the four directions
 #pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-        cplx acc[9];
-        for (int q = 0; q < 9; ++q) acc[q] = {0.0, 0.0};
-        if (active) {
-            const int nb = nbr[((size_t)p * 8 + mu) * g.Vh + cb];
-            const size_t na = (size_t)cb * Ls + s, nn = (size_t)nb * Ls + (Ls - 1 - s);
+    for (int sys = 0; sys < 2; ++sys) {
+        const double2* a = sys ? ownR : ownL;
+        const double2* b = sys ? othR : othL;
+        double2 own[12];
+        for (int q = 0; q < 12; ++q) own[q] = active ? a[q * N + na] : make_double2(0.0, 0.0);
 #pragma unroll 1
-            for (int sys = 0; sys < 2; ++sys) {
-                const double2* a = sys ? ownR : ownL;
-                const double2* b = sys ? othR : othL;
-                const double sg = sys ? -1.0 : 1.0;
+        for (int mu = 0; mu < 4; ++mu) {
+            cplx acc[9];
+            for (int q = 0; q < 9; ++q) acc[q] = {0.0, 0.0};
+            if (active) {
+                const int nb = nbr[((size_t)p * 8 + mu) * g.Vh + cb];
+                const size_t nn = (size_t)nb * Ls + (Ls - 1 - s);
                 cplx h[2][3], gg[2][3];
                 for (int cc = 0; cc < 3; ++cc) {
-                    const double2 a0 = a[cc * N + na], a1 = a[(3 + cc) * N + na];
-                    const double2 a2 = a[(6 + cc) * N + na], a3 = a[(9 + cc) * N + na];
                     const double2 b0 = b[cc * N + nn], b1 = b[(3 + cc) * N + nn];
                     const double2 b2 = b[(6 + cc) * N + nn], b3 = b[(9 + cc) * N + nn];
                     cplx p0, p1, q0, q1;
-                    amul(mu, {a2.x, a2.y}, {a3.x, a3.y}, p0, p1);
+                    amul(mu, {own[6 + cc].x, own[6 + cc].y}, {own[9 + cc].x, own[9 + cc].y}, p0, p1);
                     amul(mu, {b2.x, b2.y}, {b3.x, b3.y}, q0, q1);
-                    h[0][cc] = {a0.x + p0.r, a0.y + p0.i};
-                    h[1][cc] = {a1.x + p1.r, a1.y + p1.i};
+                    h[0][cc] = {own[cc].x + p0.r, own[cc].y + p0.i};
+                    h[1][cc] = {own[3 + cc].x + p1.r, own[3 + cc].y + p1.i};
                     gg[0][cc] = {b0.x - q0.r, b0.y - q0.i};
                     gg[1][cc] = {b1.x - q1.r, b1.y - q1.i};
                 }
@@ -124,24 +127,25 @@ __global__ void __launch_bounds__(256, 3) k_force_dev(const double2* __restrict_
                     for (int x = 0; x < 3; ++x)
                         for (int y = 0; y < 3; ++y) {
                             const cplx t = cmulc(h[j][x], gg[j][y]);
-                            acc[3 * x + y].r += sg * t.r;
-                            acc[3 * x + y].i += sg * t.i;
+                            acc[3 * x + y].r += t.r;
+                            acc[3 * x + y].i += t.i;
                         }
             }
+            for (int q = 0; q < 9; ++q) {
+                red[tid * 19 + 2 * q] = acc[q].r;
+                red[tid * 19 + 2 * q + 1] = acc[q].i;
+            }
+            __syncthreads();
+            // sum over s in a fixed order into sums[mu][site][18]: chi_L minus chi_R
+            for (int t = tid; t < NS * 18; t += NT) {
+                const int j = t / 18, q = t - 18 * j;
+                double v = 0;
+                for (int u = 0; u < Ls; ++u) v += red[(j * Ls + u) * 19 + q];
+                double* dst = sums + mu * NS * 18 + t;
+                *dst = sys ? *dst - v : v;
+            }
+            __syncthreads();
         }
-        for (int q = 0; q < 9; ++q) {
-            red[tid * 19 + 2 * q] = acc[q].r;
-            red[tid * 19 + 2 * q + 1] = acc[q].i;
-        }
-        __syncthreads();
-        // sum over s in a fixed order: sums[mu][site][18]
-        for (int t = tid; t < NS * 18; t += NT) {
-            const int j = t / 18, q = t - 18 * j;
-            double v = 0;
-            for (int u = 0; u < Ls; ++u) v += red[(j * Ls + u) * 19 + q];
-            sums[mu * NS * 18 + t] = v;
-        }
-        __syncthreads();
     }
     // one work-item per (site, mu) finishes the links
     for (int t = tid; t < 4 * NS; t += NT) {

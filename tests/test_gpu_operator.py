@@ -76,3 +76,16 @@ def test_deterministic(setup):
     a = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, eo=True).cpu().numpy()
     b = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, eo=True).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_force_parity_shapes(setup):
+    """Eq. (3.2) force kernel on every shape above (ragged workgroup tails,
+    Ls = 1, periodic time) for arbitrary chi_L, chi_R, against the oracle."""
+    lat, U, psi, ctx = setup
+    m1, m2 = MASSES[1]
+    chiL = psi
+    chiR = din.gaussian_5d(lat.L, lat.Ls, 13)
+    F, G, _ = ctx.eofa_force(m1, m2, chiL=to_dev(chiL), chiR=to_dev(chiR), want_grad=True)
+    Fr, Gr = oracle.force(lat, U, m1, m2, chiL, chiR)
+    assert np.abs(F.cpu().numpy() - Fr).max() <= 1e-12 * np.abs(Fr).max()
+    assert np.abs(G.cpu().numpy() - Gr).max() <= 1e-12 * np.abs(Gr).max()
