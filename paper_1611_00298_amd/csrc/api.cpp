@@ -806,7 +806,8 @@ void free_ctx(eofa_ctx* c) {
 // which are still in that XCD's L2, and only the tile's faces across the
 // other directions are read again by the neighbouring tile.  Rows of x hold
 // consecutive checkerboard indices, so the table is the same for both
-// parities.  Returns the natural order if the split does not divide.
+// parities.  The sweep may be cut into chunks of ext[sweep] slices.
+// Returns the natural order if the split does not divide.
 struct Tiling { int split, sweep, ext[3]; };   // dims 1 = y, 2 = z, 3 = t
 
 std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
@@ -825,9 +826,13 @@ std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
         for (int X = 0; X < 8; ++X) {
             lo[T.split] = X * (c->L[T.split] / 8);
             hi[T.split] = lo[T.split] + c->L[T.split] / 8;
+            // the sweep runs in chunks of ext[sweep] slices (all tiles of the
+            // slab visit one chunk before the next); <= 1 means one chunk
+            const int cw = ext[T.sweep] > 1 ? ext[T.sweep] : hi[T.sweep] - lo[T.sweep];
+            for (int c0 = lo[T.sweep]; c0 < hi[T.sweep]; c0 += cw)
             for (int a0 = lo[od[0]]; a0 < hi[od[0]]; a0 += ext[od[0]])
                 for (int a1 = lo[od[1]]; a1 < hi[od[1]]; a1 += ext[od[1]])
-                    for (int v = lo[T.sweep]; v < hi[T.sweep]; ++v) {
+                    for (int v = c0; v < std::min(c0 + cw, hi[T.sweep]); ++v) {
                         int b[4], e[4];
                         b[od[0]] = a0; e[od[0]] = std::min(a0 + ext[od[0]], hi[od[0]]);
                         b[od[1]] = a1; e[od[1]] = std::min(a1 + ext[od[1]], hi[od[1]]);
