@@ -130,6 +130,54 @@ def cpu_baseline(pre, seconds=12.0):
                       f"({dt:.1f} s, FP64, OpenMP)"}
 
 
+def dslash(args):
+    """Operator rates on the 24^3x64, Ls = 24 workload in every precision: the
+    even-odd Schur operator Mhat and Mhat^dag (two hopping-kernel launches
+    each, K1/K2 and K3/K4 forms) on a Gaussian half field, 10 applications
+    per direction after 2 untimed ones, HIP events on the context stream.
+    Prints one JSON line with the hopping kernel's average launch time,
+    algorithmic bytes and rate per precision against the 8 TB/s peak."""
+    import torch
+    import dwf_inputs as din
+    from paper_1611_00298_amd import Context
+
+    pre = din.preset(args.workload)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    log(f"dslash: generating {args.workload} inputs")
+    U = t(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"]))
+    psi = t(din.gaussian_5d(pre["L"], pre["Ls"], 303))
+    ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
+    n4 = pre["L"][0] * pre["L"][1] * pre["L"][2] * pre["L"][3] // 2 * pre["Ls"]
+    ref_gbs = elementwise_reference(dev)
+    out = {"metric": "dslash GFLOP/s & % HBM roofline per precision (1 GPU)",
+           "config": {"workload": f"Moebius DWF even-odd Schur operator {'x'.join(map(str, pre['L']))}, "
+                                  f"Ls={pre['Ls']}, alpha={pre['alpha']}, M5={pre['M5']}, m={pre['m1']}",
+                      "applications": 20},
+           "elementwise_ref_GBs": ref_gbs, "precisions": {}}
+    for prec in ("fp64", "fp32", "fp16", "bf16"):
+        cls = {"fp64": "hop64", "fp32": "hop32", "fp16": "hop16", "bf16": "hopb16"}[prec]
+        for dag in (False, True):
+            ctx.dwf_apply(psi, pre["m1"], pre["m1"], dagger=dag, eo=True, prec=prec)
+        torch.cuda.synchronize()
+        ctx.timing_enable(True)
+        for _ in range(10):
+            for dag in (False, True):
+                ctx.dwf_apply(psi, pre["m1"], pre["m1"], dagger=dag, eo=True, prec=prec)
+        q = ctx.timing_query(cls)
+        ctx.timing_enable(False)
+        avg_ms = q["ms"] / q["count"]
+        gbs = q["bytes"] / (q["ms"] * 1e-3) / 1e9
+        out["precisions"][prec] = {
+            "launches": q["count"], "avg_ms": avg_ms, "avg_bytes": q["bytes"] / q["count"],
+            "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS, "frac_of_elementwise_ref": gbs / ref_gbs,
+            "hop_gflops": 1320.0 * n4 / (avg_ms * 1e-3) / 1e9}
+        log(f"dslash {prec}: {avg_ms:.4f} ms per hop launch, {gbs:.0f} GB/s algorithmic")
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def trajectory(args):
     """The 24^3x64, Ls = 24 trajectory workload (c5): a fermion-only EOFA
     leapfrog trajectory of n_steps x dt from seeded links, pseudofermion and
@@ -203,6 +251,8 @@ def main():
     ap.add_argument("--trajectory", action="store_true",
                     help="instead of the step benchmark: the 24^3x64 fermion-only trajectory workload (c5), "
                          "mixed vs FP64 dH and reversibility")
+    ap.add_argument("--dslash", action="store_true",
+                    help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 x 2 GiB device copies first (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -213,6 +263,8 @@ def main():
 
     if args.trajectory:
         return trajectory(args)
+    if args.dslash:
+        return dslash(args)
 
     import torch
     import dwf_inputs as din

@@ -48,7 +48,7 @@ hipError_t launch_zero(int prec, void* f, float* fn, size_t n5, size_t N, int nb
 hipError_t launch_ingest_gauge(const void* U, void* G, int* nbr, const int L[4], int Ls, int aperiodic,
                                hipStream_t st);
 hipError_t launch_gauge_convert(int po, const void* in, void* out, size_t n, hipStream_t st);
-hipError_t launch_gauge_h16(const void* in, void* out, int Vh, hipStream_t st);
+hipError_t launch_gauge_c16(const void* in, void* out, int Vh, int bf, hipStream_t st);
 hipError_t launch_nat5_to_dev(const void* nat, void* de, void* dodd, const int L[4], int Ls, size_t N,
                               hipStream_t st);
 hipError_t launch_dev_to_nat5(void* nat, const void* de, const void* dodd, const int L[4], int Ls,
@@ -119,6 +119,7 @@ struct eofa_ctx {
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
     void* frag = nullptr;        // compact FP16 links for the matrix-core FP16 hop (4 | Ls)
+    void* frag_b = nullptr;      // compact BF16 links for the matrix-core BF16 hop (4 | Ls)
     double* om = nullptr;
     std::vector<double> om_h;
     double* partial = nullptr;
@@ -261,12 +262,14 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
     a.nbr = c->nbr + (size_t)h.par * 8 * c->Vh;
     a.sites = c->sites[h.prec];
-    if (h.prec == P16 && c->Ls % 4 == 0 && c->use_mfma) {
-        if (!c->frag) {
-            hipchk(hipMalloc(&c->frag, (size_t)2 * 8 * c->Vh * 36), "hipMalloc(FP16 links)");
-            hipchk(launch_gauge_h16(c->gauge[P64], c->frag, c->Vh, c->st), "FP16 links");
+    if ((h.prec == P16 || h.prec == PB16) && c->Ls % 4 == 0 && c->use_mfma) {
+        const int bf = h.prec == PB16;
+        void*& fr = bf ? c->frag_b : c->frag;
+        if (!fr) {
+            hipchk(hipMalloc(&fr, (size_t)2 * 8 * c->Vh * 36), "hipMalloc(16-bit links)");
+            hipchk(launch_gauge_c16(c->gauge[P64], fr, c->Vh, bf, c->st), "16-bit links");
         }
-        a.frag = (const char*)c->frag + (size_t)h.par * 8 * c->Vh * 36;
+        a.frag = (const char*)fr + (size_t)h.par * 8 * c->Vh * 36;
         a.depth = c->mfma_depth;
     }
     a.Vh = c->Vh;
@@ -786,6 +789,7 @@ void free_ctx(eofa_ctx* c) {
     if (c->nbr) hipFree(c->nbr);
     if (c->U_nat) hipFree(c->U_nat);
     if (c->frag) hipFree(c->frag);
+    if (c->frag_b) hipFree(c->frag_b);
     if (c->om) hipFree(c->om);
     if (c->partial) hipFree(c->partial);
     if (c->sc) hipFree(c->sc);
@@ -890,7 +894,8 @@ void load_gauge(eofa_ctx* c, const void* U) {
     const size_t nc = (size_t)2 * 8 * 9 * c->Vh;
     for (int p = 1; p < 4; ++p)
         if (c->gauge[p]) hipchk(launch_gauge_convert(p, c->gauge[P64], c->gauge[p], nc, c->st), "gauge convert");
-    if (c->frag) hipchk(launch_gauge_h16(c->gauge[P64], c->frag, c->Vh, c->st), "FP16 links");
+    if (c->frag) hipchk(launch_gauge_c16(c->gauge[P64], c->frag, c->Vh, 0, c->st), "FP16 links");
+    if (c->frag_b) hipchk(launch_gauge_c16(c->gauge[P64], c->frag_b, c->Vh, 1, c->st), "BF16 links");
 }
 
 }  // namespace

@@ -343,10 +343,11 @@ __device__ __forceinline__ void reconstruct_f(const float (&u)[12], float f, flo
 }
 
 struct MStage {
-    uint32_t w[12];   // raw FP16 neighbour spinor
+    uint32_t w[12];   // raw 16-bit neighbour spinor (word c = complex c as (re, im))
     float nrm;
 };
 
+template <int P>
 __device__ __forceinline__ void load_mstage(const HopArgs& a, int s, int nb, MStage& st) {
     const uint32_t n = (uint32_t)nb * a.Ls + s;
     const uint32_t off = n * 16u;
@@ -355,7 +356,8 @@ __device__ __forceinline__ void load_mstage(const HopArgs& a, int s, int nb, MSt
         const uint4 t = at<uint4>(a.in, (size_t)b * a.N * 16, off);
         st.w[4 * b] = t.x; st.w[4 * b + 1] = t.y; st.w[4 * b + 2] = t.z; st.w[4 * b + 3] = t.w;
     }
-    st.nrm = a.in_nrm[n];
+    if constexpr (P == P16) st.nrm = a.in_nrm[n];
+    else st.nrm = 1.0f;
 }
 
 // lrec: the staged link record of this direction (8 rows of 16 bytes)
@@ -387,40 +389,106 @@ __device__ __forceinline__ void compute_mstage(const MStage& st, const unsigned 
     reconstruct_f<MU, SG>(u, st.nrm, acc);
 }
 
-template <bool DAG>
+// BF16 on the matrix cores: the spin projection runs in FP32 on the
+// unpacked words and is rounded back to BF16 (v_cvt_pk_bf16_f32) for the B
+// operand; links, MFMA layout and reconstruction are those of the FP16 path
+// (BF16 fields carry no site norm).
+typedef short s4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ s4v s4_of(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(s4v, make_uint2(a, b));
+}
+__device__ __forceinline__ float b16lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float b16hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ uint32_t pack_b16(float re, float im) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)re) |
+           ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)im) << 16);
+}
+
+// h_j (j = 0, 1) for colours c = 0..2 as packed (re, im) BF16 words, the
+// same projection as project() on the stored words
+template <int MU, int SG>
+__device__ __forceinline__ void project_b16(const uint32_t (&w)[12], uint32_t (&h)[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float r0 = b16lo(w[c]), i0 = b16hi(w[c]), r1 = b16lo(w[3 + c]), i1 = b16hi(w[3 + c]);
+        const float r2 = b16lo(w[6 + c]), i2 = b16hi(w[6 + c]), r3 = b16lo(w[9 + c]), i3 = b16hi(w[9 + c]);
+        if constexpr (MU == 0) {
+            h[c] = pack_b16(r0 + SG * i3, i0 - SG * r3);  h[3 + c] = pack_b16(r1 + SG * i2, i1 - SG * r2);
+        } else if constexpr (MU == 1) {
+            h[c] = pack_b16(r0 - SG * r3, i0 - SG * i3);  h[3 + c] = pack_b16(r1 + SG * r2, i1 + SG * i2);
+        } else if constexpr (MU == 2) {
+            h[c] = pack_b16(r0 + SG * i2, i0 - SG * r2);  h[3 + c] = pack_b16(r1 - SG * i3, i1 + SG * r3);
+        } else {
+            h[c] = pack_b16(r0 + SG * r2, i0 + SG * i2);  h[3 + c] = pack_b16(r1 + SG * r3, i1 + SG * i3);
+        }
+    }
+}
+
+template <bool DAG, int D>
+__device__ __forceinline__ void compute_mstage_b16(const MStage& st, const unsigned char* lrec, int lane4,
+                                                   float (&acc)[24]) {
+    constexpr int MU = D & 3;
+    constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
+    uint32_t h[6];
+    project_b16<MU, SG>(st.w, h);
+    const uint4 r0 = *reinterpret_cast<const uint4*>(lrec + 16 * lane4);
+    const uint4 r1 = *reinterpret_cast<const uint4*>(lrec + 64 + 16 * lane4);
+    const s4v A00 = s4_of(r0.x, r0.y), A01 = s4_of(r0.z, r0.w);
+    const s4v A10 = s4_of(r1.x, r1.y), A11 = s4_of(r1.z, r1.w);
+    float u[12];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const s4v B0 = s4_of(h[3 * j], h[3 * j + 1]);
+        const s4v B1 = s4_of(h[3 * j + 2], 0u);
+        f4v c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        c0 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A00, B0, c0, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A01, B1, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A10, B0, c1, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(A11, B1, c1, 0, 0, 0);
+        u[6 * j + 0] = c0[0]; u[6 * j + 1] = c0[1]; u[6 * j + 2] = c0[2]; u[6 * j + 3] = c0[3];
+        u[6 * j + 4] = c1[0]; u[6 * j + 5] = c1[1];
+    }
+    reconstruct_f<MU, SG>(u, 1.0f, acc);
+}
+
+template <int P, bool DAG>
 __device__ __forceinline__ void compute_mstage_rt(const MStage& st, int d, const unsigned char* lrec, int lane4,
                                                   float (&acc)[24]) {
+#define EOFA_MSTAGE(DD)                                                   \
+    if constexpr (P == P16) compute_mstage<DAG, DD>(st, lrec, lane4, acc); \
+    else compute_mstage_b16<DAG, DD>(st, lrec, lane4, acc);
     switch (d) {   // d is a compile-time constant after unrolling
-    case 0: compute_mstage<DAG, 0>(st, lrec, lane4, acc); break;
-    case 1: compute_mstage<DAG, 1>(st, lrec, lane4, acc); break;
-    case 2: compute_mstage<DAG, 2>(st, lrec, lane4, acc); break;
-    case 3: compute_mstage<DAG, 3>(st, lrec, lane4, acc); break;
-    case 4: compute_mstage<DAG, 4>(st, lrec, lane4, acc); break;
-    case 5: compute_mstage<DAG, 5>(st, lrec, lane4, acc); break;
-    case 6: compute_mstage<DAG, 6>(st, lrec, lane4, acc); break;
-    default: compute_mstage<DAG, 7>(st, lrec, lane4, acc); break;
+    case 0: EOFA_MSTAGE(0) break;
+    case 1: EOFA_MSTAGE(1) break;
+    case 2: EOFA_MSTAGE(2) break;
+    case 3: EOFA_MSTAGE(3) break;
+    case 4: EOFA_MSTAGE(4) break;
+    case 5: EOFA_MSTAGE(5) break;
+    case 6: EOFA_MSTAGE(6) break;
+    default: EOFA_MSTAGE(7) break;
     }
+#undef EOFA_MSTAGE
 }
 
 // eight directions with DEPTH directions' neighbour spinors in flight;
 // called by every work-item (staging barrier inside)
-template <bool DAG, int DEPTH>
+template <int P, bool DAG, int DEPTH>
 __device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int lb, unsigned char* lds, int site, int sl, int s,
                                              int lane4, float (&acc)[24]) {
-    constexpr int LB = LinkLds<P16, 1>::LB;
+    constexpr int LB = LinkLds<P, 1>::LB;
     int nb[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) nb[d] = a.nbr[(size_t)d * a.Vh + site];
     MStage st[DEPTH];
 #pragma unroll
-    for (int d = 0; d < DEPTH; ++d) load_mstage(a, s, nb[d], st[d]);
-    stage_links<P16, 1>(a, lb, lds);
+    for (int d = 0; d < DEPTH; ++d) load_mstage<P>(a, s, nb[d], st[d]);
+    stage_links<P, 1>(a, lb, lds);
     __syncthreads();
     const unsigned char* lr = lds + sl * 8 * LB;
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
-        compute_mstage_rt<DAG>(st[d % DEPTH], d, lr + d * LB, lane4, acc);
-        if (d + DEPTH < 8) load_mstage(a, s, nb[d + DEPTH], st[d % DEPTH]);
+        compute_mstage_rt<P, DAG>(st[d % DEPTH], d, lr + d * LB, lane4, acc);
+        if (d + DEPTH < 8) load_mstage<P>(a, s, nb[d + DEPTH], st[d % DEPTH]);
     }
 }
 
@@ -579,7 +647,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
             stage_links<P, 0>(a, lb, smem_raw);
             __syncthreads();
         }
-        if constexpr (MF) hop_all_mfma<DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
+        if constexpr (MF) hop_all_mfma<P, DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
         else if constexpr (P == P64) { if (active) hop_all<P, DAG>(a, lb, smem_raw, site, sl, s, v); }
         else hop_all<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
         if (!active) {
@@ -753,7 +821,7 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     const bool need_lds = HOP ? (a.opA.kind != 0 || a.opC.kind != 0 || (a.aux && (a.opB.kind != 0 || a.opB2.kind != 0)))
                               : (a.opB.kind != 0 || a.opC.kind != 0);
     const size_t tile = need_lds ? (size_t)STR * NT * sizeof(A) : 0;
-    if constexpr (P == P16 && HOP) {
+    if constexpr ((P == P16 || P == PB16) && HOP) {
         if (a.frag) {
             const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 1>::LB, a.NS));
             if (a.depth >= 4) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 4>), dim3(nblk), dim3(NT), shm, st, a);

@@ -51,18 +51,18 @@ __global__ void k_gauge_convert(const double2* __restrict__ in, void* __restrict
     }
 }
 
-// FP64 links -> compact FP16 links for the matrix-core hop, [p][d][Vh][9]
-// complex numbers as (re, im) half pairs (36 bytes per link; the hop expands
-// them into the rows of the real 6x6 form when it stages them in LDS).
-// One work-item per (p, d, cb).
-__global__ void k_gauge_h16(const double2* __restrict__ in, uint32_t* __restrict__ out, int Vh) {
+// FP64 links -> compact 16-bit links for the matrix-core hop, [p][d][Vh][9]
+// complex numbers as (re, im) pairs of FP16 (bf = 0) or BF16 (bf = 1), 36
+// bytes per link; the hop expands them into the rows of the real 6x6 form
+// when it stages them in LDS.  One work-item per (p, d, cb).
+__global__ void k_gauge_c16(const double2* __restrict__ in, uint32_t* __restrict__ out, int Vh, int bf) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * 8 * Vh) return;
     const int pd = t / Vh, cb = t - pd * Vh;
     uint32_t* o = out + ((size_t)pd * Vh + cb) * 9;
     for (int k = 0; k < 9; ++k) {
         const double2 u = in[((size_t)pd * 9 + k) * Vh + cb];
-        o[k] = f2h((float)u.x) | (f2h((float)u.y) << 16);
+        o[k] = bf ? (f2b((float)u.x) | (f2b((float)u.y) << 16)) : (f2h((float)u.x) | (f2h((float)u.y) << 16));
     }
 }
 
@@ -225,9 +225,10 @@ hipError_t launch_eofa_source(const void* phi, const double* om, void* bLe, void
     return hipGetLastError();
 }
 
-hipError_t launch_gauge_h16(const void* in, void* out, int Vh, hipStream_t st) {
+hipError_t launch_gauge_c16(const void* in, void* out, int Vh, int bf, hipStream_t st) {
     const int n = 2 * 8 * Vh;
-    hipLaunchKernelGGL(k_gauge_h16, dim3((n + 255) / 256), dim3(256), 0, st, (const double2*)in, (uint32_t*)out, Vh);
+    hipLaunchKernelGGL(k_gauge_c16, dim3((n + 255) / 256), dim3(256), 0, st, (const double2*)in, (uint32_t*)out, Vh,
+                       bf);
     return hipGetLastError();
 }
 
