@@ -258,11 +258,14 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.aux_nrm = h.aux ? h.aux->nrm : nullptr;
     a.aux2 = h.aux2 ? h.aux2->d : nullptr;
     a.aux2_nrm = h.aux2 ? h.aux2->nrm : nullptr;
-    const int lp = link_prec(h.prec);
-    a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
     a.nbr = c->nbr + (size_t)h.par * 8 * c->Vh;
     a.sites = c->sites[h.prec];
-    if ((h.prec == P16 || h.prec == PB16) && c->Ls % 4 == 0 && c->use_mfma) {
+    const bool mfma = (h.prec == P16 || h.prec == PB16) && c->Ls % 4 == 0 && c->use_mfma;
+    if (h.hop && !mfma) {   // the matrix-core paths read only their compact 16-bit links
+        const int lp = link_prec(h.prec);
+        a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
+    }
+    if (h.hop && mfma) {
         const int bf = h.prec == PB16;
         void*& fr = bf ? c->frag_b : c->frag;
         if (!fr) {
@@ -531,6 +534,11 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
         // idle GPU; decisions therefore use the estimate one iteration late.
         double rr_est = rr;
         int pend_cur = -1;          // slot of |z_k|^2 of the pending ring entry, -1: none
+        // Stagnation guard: in 16-bit arithmetic the recursion can stall
+        // (lost conjugacy) with the estimate above delta |r|.  A segment
+        // longer than max(400, 4 x the longest one so far) forces a reliable
+        // update and restarts the directions from z.
+        int seg_iters = 0, seg_max = 0;
         while (res.iters < maxiter) {
             Half& p = *pr[k % XBATCH];
             schur_k1(c, prec, p, tmp, mp, mm);
@@ -554,7 +562,10 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
             }
             pend_cur = cur;
             const double rn = std::sqrt(std::max(rr_est, 0.0));
-            if (rn <= delta * rmax || rn <= thresh) {
+            ++seg_iters;
+            const bool stalled = seg_iters > std::max(400, 4 * seg_max);
+            bool restart = false;
+            if (rn <= delta * rmax || rn <= thresh || stalled) {
                 // reliable update: fold the directions into x_lo, x_lo into x, recompute r in FP64
                 flush(k);
                 fold_x();
@@ -564,6 +575,9 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
                 rmax = std::sqrt(rr);
                 rr_est = rr;
                 pend_cur = -1;   // the true residual includes iteration k
+                seg_max = std::max(seg_max, seg_iters);
+                seg_iters = 0;
+                restart = stalled;
                 if (rmax <= thresh) { res.converged = true; break; }
                 convert(c, r64, r);
                 schur_k3(c, prec, r, tmp, mp, mm);
@@ -573,7 +587,7 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
             if (k - pending0 + 1 == XBATCH) flush(k);
             if (res.iters >= maxiter) { flush(k); break; }
             Half& pn1 = *pr[(k + 1) % XBATCH];
-            pupdate(c, prec, z, &p, pn1, nullptr, nxt, cur, mp, mm);
+            pupdate(c, prec, z, restart ? nullptr : &p, pn1, nullptr, nxt, cur, mp, mm);
             c->flops += 72.0 * (double)c->n5 + 48.0 * (double)c->n5;
             std::swap(cur, nxt);
             ++k;

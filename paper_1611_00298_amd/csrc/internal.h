@@ -192,34 +192,12 @@ __device__ __forceinline__ float ld_spinor_raw(const void* __restrict__ base, co
 }
 
 // ---------------------------------------------------------------------------
-// links: complex k (row-major 3x3) of direction d at output site.  FP64
-// fields use FP64 links; every lower precision uses FP32 links (their
-// bytes are shared by the Ls slices of a 4D site, so FP32 costs little
-// traffic and saves the 16-bit conversions).
+// links, [p][d][9][Vh] complex (row-major 3x3): FP64 fields use FP64 links;
+// the FP32 and vector 16-bit paths use FP32 links (their bytes are shared by
+// the Ls slices of a 4D site, so FP32 costs little traffic and saves the
+// 16-bit conversions); the matrix-core paths use compact 16-bit copies.
 // ---------------------------------------------------------------------------
 constexpr int link_prec(int p) { return p == P64 ? P64 : P32; }
-
-template <int P>
-__device__ __forceinline__ void ld_link(const void* __restrict__ g, int d, int site, int Vh,
-                                        typename PT<P>::A (&u)[18]) {
-    if constexpr (P == P64) {
-        const size_t bb = (size_t)Vh * 16;
-        const uint32_t off = (uint32_t)site * 16u;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const double2 t = at<double2>(g, (size_t)(d * 9 + k) * bb, off);
-            u[2 * k] = t.x; u[2 * k + 1] = t.y;
-        }
-    } else {
-        const size_t bb = (size_t)Vh * 8;
-        const uint32_t off = (uint32_t)site * 8u;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const float2 t = at<float2>(g, (size_t)(d * 9 + k) * bb, off);
-            u[2 * k] = t.x; u[2 * k + 1] = t.y;
-        }
-    }
-}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumber them so that XCD x works on one contiguous range of
