@@ -307,3 +307,123 @@ def md_update(U, P, F, dt_p, dt_u):
 def kinetic(P) -> float:
     """sum over links of tr(P^2) = (1/2) sum_a (p^a)^2."""
     return float((P * np.swapaxes(P, -1, -2)).sum().real)
+
+
+# ---------------------------------------------------------------------------
+# heatbath (Section 3.1, eq. (3.1)) -- plain numpy on top of H_op
+# ---------------------------------------------------------------------------
+
+def zolotarev_inv_sqrt(lo: float, hi: float, n: int):
+    """Best relative-error approximation of x^(-1/2) on [lo, hi] by a
+    rational function of type (n, n), in the partial-fraction form that
+    eq. (3.1) starts from: x^(-1/2) ~ a0 + sum_l a_l / (b_l + x).
+
+    Zolotarev's closed form on y = x/lo in [1, kappa], kappa = hi/lo:
+    R0(y) = prod_l (y + c_{2l}) / (y + c_{2l-1}) with
+    c_j = sn^2(u_j | m) / cn^2(u_j | m), u_j = j K(m) / (2n + 1),
+    m = 1 - 1/kappa (Jacobi elliptic functions of parameter m).
+    sqrt(y) R0(y) has its smallest value at y = 1 and its largest at
+    y = kappa, and the scale d = 2 / (min + max) makes the relative error
+    equioscillate with magnitude delta = (max - min) / (max + min).
+    Returns (a0, a, b, delta)."""
+    from scipy.special import ellipj, ellipk
+    if not (0 < lo <= hi) or n < 1:
+        raise ValueError("need 0 < lo <= hi and n >= 1")
+    kappa = hi / lo
+    m = 1.0 - 1.0 / kappa
+    u = np.arange(1, 2 * n + 1) * ellipk(m) / (2 * n + 1)
+    sn, cn, _, _ = ellipj(u, m)
+    c = (sn / cn) ** 2
+    poles, zeros = c[0::2], c[1::2]
+    R0 = lambda y: np.prod((y + zeros) / (y + poles))
+    fmin, fmax = R0(1.0), np.sqrt(kappa) * R0(kappa)
+    d = 2.0 / (fmin + fmax)
+    delta = abs(fmax - fmin) / (fmax + fmin)
+    # back to x: lo^(-1/2) d prod (x + lo c_2l) / (x + lo c_2l-1), then partial fractions
+    A, B = lo * zeros, lo * poles
+    a0 = d / np.sqrt(lo)
+    a = np.array([a0 * np.prod(A - B[l]) / np.prod(np.delete(B, l) - B[l]) for l in range(n)])
+    return float(a0), a, B.copy(), float(delta)
+
+
+def rational_eval(a0, a, b, x):
+    """a0 + sum_l a_l / (b_l + x)."""
+    x = np.asarray(x, dtype=np.float64)
+    return a0 + sum(al / (bl + x) for al, bl in zip(a, b))
+
+
+def embed_omega(lat: Lattice, om, v4, lower: bool):
+    """The 5D field Omega(s) P v(x): P = P_- (spins 2,3) if lower, else P_+."""
+    out = lat.zeros5()
+    sl = slice(2, 4) if lower else slice(0, 2)
+    out[..., sl, :] = np.asarray(om)[:, None, None, None, None, None, None] * v4[None, ..., sl, :]
+    return out
+
+
+def project_omega(lat: Lattice, om, psi, lower: bool):
+    """The 4D field P Omega^dag psi = sum_s Omega(s) P psi(s)."""
+    out = np.zeros(lat.shape4 + (4, 3), dtype=np.complex128)
+    sl = slice(2, 4) if lower else slice(0, 2)
+    out[..., sl, :] = np.einsum("s,s...->...", np.asarray(om), psi[..., sl, :])
+    return out
+
+
+def shifted_H(lat: Lattice, U, m1, m2, which: str, g, psi):
+    """The operators inverted in eq. (3.1), with Delta_pm = k Omega_pm Omega_pm^dag:
+    'L': [H(m1) - g Delta_- P_-] psi;   'R': [H(m2) - g Delta_+ P_+] psi."""
+    om_m, om_p, k = omega_k(lat, m1, m2)
+    if which == "L":
+        return H_op(lat, U, m1, m1, psi) - g * k * embed_omega(
+            lat, om_m, project_omega(lat, om_m, psi, True), True)
+    return H_op(lat, U, m2, m2, psi) - g * k * embed_omega(
+        lat, om_p, project_omega(lat, om_p, psi, False), False)
+
+
+def cg_hermitian(op, b, tol=1e-12, maxiter=100000):
+    """Solve op x = b for a Hermitian (possibly indefinite) op by CG on
+    op^2 x = op b.  Returns (x, iterations, |b - op x| / |b|)."""
+    x = np.zeros_like(b)
+    bn = np.linalg.norm(b)
+    if bn == 0:
+        return x, 0, 0.0
+    r = op(b)               # residual of the normal equations at x = 0
+    p = r.copy()
+    rr = np.vdot(r, r).real
+    it = 0
+    while it < maxiter:
+        w = op(p)
+        al = rr / np.vdot(w, w).real
+        x += al * p
+        it += 1
+        res = np.linalg.norm(b - op(x)) / bn
+        if res <= tol:
+            break
+        r -= al * op(w)
+        rn = np.vdot(r, r).real
+        p = r + (rn / rr) * p
+        rr = rn
+    return x, it, float(np.linalg.norm(b - op(x)) / bn)
+
+
+def eofa_heatbath(lat: Lattice, U, m1, m2, eta, a0, a, b, tol=1e-12, maxiter=100000):
+    """phi ~ M_EOFA^(-1/2) eta by eq. (3.1): with gamma_l = 1/(1 + b_l),
+    phi = a0 eta + sum_l a_l gamma_l { eta
+            + k gamma_l P_- Omega_-^dag [H(m1) - gamma_l Delta_- P_-]^-1 Omega_- P_- eta
+            - k gamma_l P_+ Omega_+^dag [H(m2) - gamma_l b_l Delta_+ P_+]^-1 Omega_+ P_+ eta }.
+    Two solves per pole.  Returns (phi, iterations per solve)."""
+    om_m, om_p, k = omega_k(lat, m1, m2)
+    eta = _c128(eta)
+    phi = a0 * eta
+    vL = embed_omega(lat, om_m, eta, True)
+    vR = embed_omega(lat, om_p, eta, False)
+    its = []
+    for al, bl in zip(a, b):
+        g = 1.0 / (1.0 + bl)
+        yL, iL, rL = cg_hermitian(lambda v: shifted_H(lat, U, m1, m2, "L", g, v), vL, tol, maxiter)
+        yR, iR, rR = cg_hermitian(lambda v: shifted_H(lat, U, m1, m2, "R", g * bl, v), vR, tol, maxiter)
+        if rL > tol or rR > tol:
+            raise RuntimeError("oracle heatbath solve did not converge")
+        its += [iL, iR]
+        phi = phi + al * g * (eta + k * g * project_omega(lat, om_m, yL, True)
+                              - k * g * project_omega(lat, om_p, yR, False))
+    return phi, its

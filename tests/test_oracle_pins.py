@@ -514,3 +514,108 @@ def test_md_exponential():
     # kinetic term: tr P^2 = (1/2) sum_a (p^a)^2
     p = din.rng(7).standard_normal((4, 2, 2, 2, 2, 8))
     assert oracle.kinetic(P) == pytest.approx(0.5 * (p ** 2).sum(), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# heatbath (Section 3.1, eq. (3.1))
+# --------------------------------------------------------------------------
+
+def alternation_runs(e, level):
+    """Number of same-sign runs among the samples where |e| reaches level."""
+    s = np.sign(e[np.abs(e) >= level])
+    return 1 + int(np.sum(s[1:] != s[:-1]))
+
+
+@pytest.mark.parametrize("lo,hi,n", [(0.5, 5.0, 3), (0.9, 2.7, 4), (1.0, 100.0, 6), (0.2, 0.3, 2),
+                                     (0.05, 50.0, 10)])
+def test_zolotarev_equioscillation(lo, hi, n):
+    """Chebyshev's alternation theorem: a type (n, n) rational function whose
+    relative error against x^(-1/2) takes its extreme value with alternating
+    signs at 2n + 2 points is the best one, so the returned coefficients are
+    the minimax approximation and delta is its error."""
+    a0, a, b, delta = oracle.zolotarev_inv_sqrt(lo, hi, n)
+    x = np.exp(np.linspace(np.log(lo), np.log(hi), 400001))
+    e = np.sqrt(x) * oracle.rational_eval(a0, a, b, x) - 1.0
+    assert np.abs(e).max() == pytest.approx(delta, rel=1e-6)
+    assert alternation_runs(e, 0.98 * delta) == 2 * n + 2
+    assert np.all(b > 0)    # gamma_l = 1 / (1 + b_l) lies in (0, 1)
+    # one pole fewer is strictly worse
+    if n > 1:
+        assert oracle.zolotarev_inv_sqrt(lo, hi, n - 1)[3] > 2 * delta
+
+
+def test_zolotarev_degenerate_interval():
+    """lo = hi: x^(-1/2) is matched exactly at the single point."""
+    a0, a, b, delta = oracle.zolotarev_inv_sqrt(2.0, 2.0, 2)
+    assert delta == 0.0
+    assert oracle.rational_eval(a0, a, b, 2.0) == pytest.approx(2.0 ** -0.5, rel=1e-14)
+
+
+@pytest.mark.parametrize("alpha,Ls", [(1.0, 4), (2.0, 5), (4.0, 6)])
+def test_shifted_operators_are_mass_shifts(alpha, Ls):
+    """The operators of eq. (3.1) are again H(m+, m-) with one boundary mass
+    moved: with h(m) = m / N(m), N(m) = b5^Ls + m (-c5)^Ls,
+    H(m1) - g Delta_- P_- = H(m+ = m1, m- = mL), h(mL) = h(m1) + g (h(m2) - h(m1)),
+    H(m2) - g Delta_+ P_+ = H(m+ = mR, m- = m2), h(mR) = h(m2) + g (h(m1) - h(m2))."""
+    lat = Lattice((4, 2, 2, 4), Ls, M5=1.8, alpha=alpha)
+    U = din.random_gauge(lat.L, 0.3, 12)
+    psi = rand5(lat, 13)
+    m1, m2 = 0.04, 0.7
+    N = lambda m: lat.b5 ** Ls + m * (-lat.c5) ** Ls
+    h = lambda m: m / N(m)
+    hinv = lambda y: y * lat.b5 ** Ls / (1.0 - y * (-lat.c5) ** Ls)
+    for g in (0.0, 0.3, 0.8, 1.0):
+        mL = hinv(h(m1) + g * (h(m2) - h(m1)))
+        mR = hinv(h(m2) + g * (h(m1) - h(m2)))
+        A = oracle.shifted_H(lat, U, m1, m2, "L", g, psi)
+        B = oracle.shifted_H(lat, U, m1, m2, "R", g, psi)
+        scale = np.abs(A).max()
+        assert np.abs(A - oracle.H_op(lat, U, m1, mL, psi)).max() < 1e-14 * scale
+        assert np.abs(B - oracle.H_op(lat, U, mR, m2, psi)).max() < 1e-14 * scale
+        if 0 < g:   # the other chirality's mass is not the one that moves
+            assert np.abs(A - oracle.H_op(lat, U, mL, m1, psi)).max() > 1e-3 * scale
+
+
+@pytest.fixture(scope="module")
+def dense_heatbath(dense_eofa):
+    lat, U, m1, m2, H1, H12, H2 = dense_eofa
+    M = build_M_eofa(lat, U, m1, m2, H1, H12)
+    M = 0.5 * (M + M.conj().T)
+    lam, V = np.linalg.eigh(M)
+    eta = din.gaussian_4d(lat.L, 31)
+    return lat, U, m1, m2, M, lam, V, eta
+
+
+def test_heatbath_is_the_rational_function_of_M(dense_heatbath):
+    """eq. (3.1) (2 N_p solves with H) equals a0 eta + sum_l a_l (b_l + M)^-1 eta
+    with M = M_EOFA built densely: checks the Sherman-Morrison form, the
+    gamma_l b_l weight of the R-side shift and the signs."""
+    lat, U, m1, m2, M, lam, V, eta = dense_heatbath
+    a0, a, b, delta = oracle.zolotarev_inv_sqrt(0.9 * lam[0], 1.1 * lam[-1], 3)
+    phi, its = oracle.eofa_heatbath(lat, U, m1, m2, eta, a0, a, b, tol=1e-13)
+    n = M.shape[0]
+    e = eta.reshape(n)
+    ref = a0 * e + sum(al * np.linalg.solve(M + bl * np.eye(n), e) for al, bl in zip(a, b))
+    assert np.linalg.norm(phi.reshape(n) - ref) / np.linalg.norm(ref) < 1e-11
+    assert len(its) == 6 and min(its) > 0
+
+
+def test_heatbath_draws_from_M_eofa(dense_heatbath):
+    """phi = M^(-1/2) eta to within the approximation's error: with the
+    spectrum inside [lo, hi], |phi - M^(-1/2) eta| <= delta |M^(-1/2) eta|,
+    and phi^dag M phi = eta^dag eta (1 + O(delta)) (Section 3.1)."""
+    lat, U, m1, m2, M, lam, V, eta = dense_heatbath
+    assert lam[0] > 0 and lam[-1] / lam[0] > 1.05    # a non-trivial spectrum
+    n = M.shape[0]
+    e = eta.reshape(n)
+    exact = V @ ((V.conj().T @ e) / np.sqrt(lam))
+    for npole in (2, 5):
+        a0, a, b, delta = oracle.zolotarev_inv_sqrt(lam[0], lam[-1], npole)
+        phi, _ = oracle.eofa_heatbath(lat, U, m1, m2, eta, a0, a, b, tol=1e-13)
+        p = phi.reshape(n)
+        err = np.linalg.norm(p - exact) / np.linalg.norm(exact)
+        assert err <= delta * (1 + 1e-6) + 1e-11
+        if npole == 2:
+            assert err > 1e-3 * delta     # the bound is not vacuous here
+        S = np.vdot(p, M @ p).real
+        assert abs(S / np.vdot(e, e).real - 1) <= 2.01 * delta + 1e-11
