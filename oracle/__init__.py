@@ -49,6 +49,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
+        # OpenMP workers that spin after each parallel region starve the numpy
+        # code between oracle calls; let them sleep instead (read at load).
+        os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
         _lib = C.CDLL(_LIB)
         P, D, I_, L_ = C.c_void_p, C.c_double, C.c_int, C.c_long
         g = C.POINTER(Geom)
@@ -66,6 +69,8 @@ def lib():
             "orc_schur": (None, [g, P, D, D, I_, P, P]),
             "orc_solve_ddwf_eo": (I_, [g, P, D, D, P, P, D, I_, I_, P]),
             "orc_solve_H": (I_, [g, P, D, D, P, P, D, I_, P]),
+            "orc_H_shifted": (None, [g, P, D, D, I_, D, P, P]),
+            "orc_solve_H_shifted": (I_, [g, P, D, D, I_, D, P, P, D, I_, P]),
             "orc_eofa_chi": (I_, [g, P, D, D, P, P, P, I_, D, I_, P]),
             "orc_action": (None, [g, D, D, P, P, P, P, P]),
             "orc_force": (None, [g, P, D, D, P, P, P, P, P, L_]),
@@ -371,38 +376,20 @@ def project_omega(lat: Lattice, om, psi, lower: bool):
 def shifted_H(lat: Lattice, U, m1, m2, which: str, g, psi):
     """The operators inverted in eq. (3.1), with Delta_pm = k Omega_pm Omega_pm^dag:
     'L': [H(m1) - g Delta_- P_-] psi;   'R': [H(m2) - g Delta_+ P_+] psi."""
-    om_m, om_p, k = omega_k(lat, m1, m2)
-    if which == "L":
-        return H_op(lat, U, m1, m1, psi) - g * k * embed_omega(
-            lat, om_m, project_omega(lat, om_m, psi, True), True)
-    return H_op(lat, U, m2, m2, psi) - g * k * embed_omega(
-        lat, om_p, project_omega(lat, om_p, psi, False), False)
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().orc_H_shifted(lat.gp, _p(_c128(U)), m1, m2, 0 if which == "L" else 1, g, _p(psi), _p(out))
+    return out
 
 
-def cg_hermitian(op, b, tol=1e-12, maxiter=100000):
-    """Solve op x = b for a Hermitian (possibly indefinite) op by CG on
-    op^2 x = op b.  Returns (x, iterations, |b - op x| / |b|)."""
-    x = np.zeros_like(b)
-    bn = np.linalg.norm(b)
-    if bn == 0:
-        return x, 0, 0.0
-    r = op(b)               # residual of the normal equations at x = 0
-    p = r.copy()
-    rr = np.vdot(r, r).real
-    it = 0
-    while it < maxiter:
-        w = op(p)
-        al = rr / np.vdot(w, w).real
-        x += al * p
-        it += 1
-        res = np.linalg.norm(b - op(x)) / bn
-        if res <= tol:
-            break
-        r -= al * op(w)
-        rn = np.vdot(r, r).real
-        p = r + (rn / rr) * p
-        rr = rn
-    return x, it, float(np.linalg.norm(b - op(x)) / bn)
+def solve_shifted_H(lat: Lattice, U, m1, m2, which: str, g, v, tol=1e-12, maxiter=100000):
+    """Solve shifted_H(...) chi = v by CGNR.  Returns (chi, iterations, |v - A chi| / |v|)."""
+    v = _c128(v)
+    chi = np.zeros_like(v)
+    res = np.zeros(1)
+    it = lib().orc_solve_H_shifted(lat.gp, _p(_c128(U)), m1, m2, 0 if which == "L" else 1, g,
+                                   _p(v), _p(chi), tol, maxiter, _p(res))
+    return chi, it, float(res[0])
 
 
 def eofa_heatbath(lat: Lattice, U, m1, m2, eta, a0, a, b, tol=1e-12, maxiter=100000):
@@ -419,8 +406,8 @@ def eofa_heatbath(lat: Lattice, U, m1, m2, eta, a0, a, b, tol=1e-12, maxiter=100
     its = []
     for al, bl in zip(a, b):
         g = 1.0 / (1.0 + bl)
-        yL, iL, rL = cg_hermitian(lambda v: shifted_H(lat, U, m1, m2, "L", g, v), vL, tol, maxiter)
-        yR, iR, rR = cg_hermitian(lambda v: shifted_H(lat, U, m1, m2, "R", g * bl, v), vR, tol, maxiter)
+        yL, iL, rL = solve_shifted_H(lat, U, m1, m2, "L", g, vL, tol, maxiter)
+        yR, iR, rR = solve_shifted_H(lat, U, m1, m2, "R", g * bl, vR, tol, maxiter)
         if rL > tol or rR > tol:
             raise RuntimeError("oracle heatbath solve did not converge")
         its += [iL, iR]

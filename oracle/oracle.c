@@ -647,6 +647,64 @@ int orc_solve_H(const og_t *g, const double *U, double mp, double mm,
 }
 
 /* ------------------------------------------------------------------ */
+/* heatbath operators of eq. (3.1)                                       */
+/* ------------------------------------------------------------------ */
+
+typedef struct { const og_t *g; const double *U; double m; double gk; const double *om; int minus; } shctx_t;
+
+/* out = [H(m) - gk Omega Omega^dag P] in, with Omega Omega^dag P acting as
+ * (Omega Omega^dag P psi)(x,s) = Omega(s) P sum_s' Omega(s') psi(x,s');
+ * minus = 1: P_-, else P_+.  gk = g k for Delta = k Omega Omega^dag. */
+static void shifted_op(void *c, const cplx *in, cplx *out)
+{
+    const shctx_t *o = c;
+    const og_t *g = o->g;
+    const long V = vol4(g);
+    orc_H(g, o->U, o->m, o->m, (const double *)in, (double *)out);
+    cplx P[4][4];
+    chiral_projector(!o->minus, P);
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < V; i++) {
+        cplx acc[12] = {0}, pa[12];
+        for (int s = 0; s < g->Ls; s++)
+            for (int k = 0; k < 12; k++) acc[k] += o->om[s] * in[((long)s * V + i) * 12 + k];
+        spin_mat(P, acc, pa);
+        for (int s = 0; s < g->Ls; s++)
+            for (int k = 0; k < 12; k++) out[((long)s * V + i) * 12 + k] -= o->gk * o->om[s] * pa[k];
+    }
+}
+
+/* which = 0: H(m1) - g Delta_- P_-;  which = 1: H(m2) - g Delta_+ P_+. */
+void orc_H_shifted(const og_t *g, const double *U, double m1, double m2, int which, double gshift,
+                   const double *in_, double *out_)
+{
+    double *om_m = malloc(sizeof(double) * g->Ls), *om_p = malloc(sizeof(double) * g->Ls), k;
+    orc_omega_k(g, m1, m2, om_m, om_p, &k);
+    shctx_t ctx = {g, U, which ? m2 : m1, gshift * k, which ? om_p : om_m, !which};
+    shifted_op(&ctx, (const cplx *)in_, (cplx *)out_);
+    free(om_m); free(om_p);
+}
+
+/* Solve the shifted system of orc_H_shifted for chi (CGNR; the operator is
+ * Hermitian, so A^dag = A); stops when |v - A chi| < tol |v|. */
+int orc_solve_H_shifted(const og_t *g, const double *U, double m1, double m2, int which,
+                        double gshift, const double *v_, double *chi_, double tol, int maxiter,
+                        double *resid)
+{
+    const long n = len5(g);
+    double *om_m = malloc(sizeof(double) * g->Ls), *om_p = malloc(sizeof(double) * g->Ls), k;
+    orc_omega_k(g, m1, m2, om_m, om_p, &k);
+    shctx_t ctx = {g, U, which ? m2 : m1, gshift * k, which ? om_p : om_m, !which};
+    memset(chi_, 0, n * sizeof(cplx));
+    double vnorm = sqrt(norm2(n, (const cplx *)v_));
+    int it = vnorm > 0 ? cgnr(shifted_op, shifted_op, &ctx, n, (const cplx *)v_, (cplx *)chi_, vnorm,
+                              tol, maxiter, 0, resid) : 0;
+    if (vnorm == 0 && resid) *resid = 0;
+    free(om_m); free(om_p);
+    return it;
+}
+
+/* ------------------------------------------------------------------ */
 /* EOFA solutions, action and force (Sections 2, 3.1, 3.3 (force: eq. (3.2)))               */
 /* ------------------------------------------------------------------ */
 
