@@ -118,6 +118,43 @@ int eofa_solve(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
                const void *x0_L_dev, const void *x0_R_dev, void *chiL_dev, void *chiR_dev,
                void *Mphi_dev, double *S_out, const eofa_solver_t *solver, eofa_stats_t *stats);
 
+/* Rational approximation for the heatbath of Section 3.1: the best
+ * relative-error approximation of x^(-1/2) on [lo, hi] of type (n, n),
+ *   x^(-1/2) ~ alpha0 + sum_{l<n} alpha[l] / (beta[l] + x),
+ * from Zolotarev's closed form (Jacobi elliptic functions by the
+ * arithmetic-geometric mean).  The relative error alternates 2n + 2 times
+ * on [lo, hi] with magnitude *delta_out (NULL: skip); every beta[l] > 0.
+ * alpha/beta: caller-owned host arrays of n doubles.  Host computation
+ * only, no context needed.  EOFA_EINVAL unless 0 < lo <= hi < inf and
+ * 1 <= n <= 64. */
+int eofa_rational_inv_sqrt(double lo, double hi, int n, double *alpha0, double *alpha,
+                           double *beta, double *delta_out);
+
+/* EOFA heatbath of eq. (3.1): phi ~ M_EOFA^(-1/2) eta, for a rational
+ * approximation x^(-1/2) ~ alpha0 + sum_l alpha_l / (beta_l + x) and
+ * gamma_l = 1 / (1 + beta_l):
+ *   phi = alpha0 eta + sum_l alpha_l gamma_l { eta
+ *       + k gamma_l P_- Omega_-^dag [H(m1) - gamma_l Delta_- P_-]^-1 Omega_- P_- eta
+ *       - k gamma_l P_+ Omega_+^dag [H(m2) - gamma_l beta_l Delta_+ P_+]^-1 Omega_+ P_+ eta },
+ * Delta_pm = k Omega_pm Omega_pm^dag (Omega, k as for eofa_solve).  Each
+ * shifted operator is H(m+, m-) with one boundary mass moved: with
+ * h(m) = m / N(m),
+ *   H(m1) - g Delta_- P_- = H(m1, mL),  h(mL) = h(m1) + g (h(m2) - h(m1)),
+ *   H(m2) - g Delta_+ P_+ = H(mR, m2),  h(mR) = h(m2) + g (h(m1) - h(m2)),
+ * so the 2 n_poles inversions are Cayley-form even-odd solves as in
+ * eofa_solve, to `solver`'s true-residual tolerance.
+ *   eta_dev: 4D source (typically Gaussian), phi_dev: 4D output; device
+ *   pointers, natural layout, may not alias.
+ *   alpha/beta: caller-owned host arrays of n_poles doubles, beta_l > -1
+ *   (n_poles = 0, or m1 = m2 where k = 0: phi = (alpha0 + sum_l alpha_l gamma_l) eta).
+ *   stats (NULL: skip): iterations and reliable updates summed over the
+ *   poles for the L (index 0) and R (index 1) side, true_resid the largest.
+ * Requires m1 <= m2.  EOFA_ENOCONV if a solve missed the tolerance (phi is
+ * still written); EOFA_EINVAL for bad arguments or a shift with N(m) <= 0. */
+int eofa_heatbath(eofa_ctx_t *ctx, double m1, double m2, const void *eta_dev, int n_poles,
+                  double alpha0, const double *alpha, const double *beta, void *phi_dev,
+                  const eofa_solver_t *solver, eofa_stats_t *stats);
+
 /* Pseudofermion force of eq. (3.2):
  *   d^a_{x,mu} S = k chi_L^dag g5 R5 (d^a D_w) chi_L - k chi_R^dag g5 R5 (d^a D_w) chi_R,
  * d^a the derivative along U_mu(x) -> exp(i eps T^a) U_mu(x), T^a = lambda^a/2.

@@ -38,6 +38,20 @@ def make_solver(tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.3) -> S
     return Solver(float(tol), int(maxiter), PREC[inner], float(reliable_delta))
 
 
+def rational_inv_sqrt(lo, hi, n):
+    """Zolotarev's best relative-error approximation of x^(-1/2) on [lo, hi]:
+    x^(-1/2) ~ a0 + sum_l a[l] / (b[l] + x).  Returns (a0, a, b, delta) with
+    a, b lists of n floats and delta the maximal relative error."""
+    lib = _lib.load()
+    n = int(n)
+    a = (C.c_double * max(n, 1))()
+    b = (C.c_double * max(n, 1))()
+    a0 = C.c_double(0.0)
+    delta = C.c_double(0.0)
+    check(lib.eofa_rational_inv_sqrt(float(lo), float(hi), n, C.byref(a0), a, b, C.byref(delta)))
+    return a0.value, list(a)[:n], list(b)[:n], delta.value
+
+
 class Context:
     """One lattice geometry and gauge field (eofa_ctx_create)."""
 
@@ -115,6 +129,38 @@ class Context:
         d["converged"] = rc == _lib.EOFA_OK
         return chiL, chiR, Mphi, S.value, d
 
+    # -- eofa_heatbath ---------------------------------------------------------
+    def eofa_heatbath(self, eta, m1, m2, coeffs=None, lo=None, hi=None, n_poles=None, tol=1e-10,
+                      maxiter=20000, inner="fp64", reliable_delta=0.3, allow_noconv=False):
+        """phi ~ M_EOFA^(-1/2) eta (eq. (3.1)).  The rational approximation is
+        either coeffs = (a0, a, b) or Zolotarev's on [lo, hi] with n_poles.
+        Returns (phi, stats dict); stats carries the approximation error
+        "delta" when the coefficients were computed here."""
+        _want(eta, self.shape_phi, "eta")
+        delta = None
+        if coeffs is None:
+            if lo is None or hi is None or n_poles is None:
+                raise ValueError("give coeffs=(a0, a, b) or lo, hi and n_poles")
+            a0, a, b, delta = rational_inv_sqrt(lo, hi, n_poles)
+        else:
+            a0, a, b = coeffs
+        a, b = [float(v) for v in a], [float(v) for v in b]
+        if len(a) != len(b):
+            raise ValueError("a and b must have the same length")
+        n = len(a)
+        ca = (C.c_double * max(n, 1))(*a)
+        cb = (C.c_double * max(n, 1))(*b)
+        phi = torch.empty_like(eta)
+        sp = make_solver(tol, maxiter, inner, reliable_delta)
+        st = Stats()
+        rc = self.lib.eofa_heatbath(self.handle, float(m1), float(m2), _ptr(eta), n, float(a0), ca, cb,
+                                    _ptr(phi), C.byref(sp), C.byref(st))
+        check(rc, allow_noconv)
+        d = st.as_dict()
+        d["converged"] = rc == _lib.EOFA_OK
+        d["delta"] = delta
+        return phi, d
+
     # -- eofa_force ------------------------------------------------------------
     def eofa_force(self, m1, m2, phi=None, chiL=None, chiR=None, want_grad=False, tol=1e-10,
                    maxiter=20000, inner="fp64", reliable_delta=0.3):
@@ -171,6 +217,10 @@ def dwf_apply(ctx: Context, psi, m_plus, m_minus, dagger=False, eo=False, prec="
 
 def eofa_solve(ctx: Context, phi, m1, m2, **kw):
     return ctx.eofa_solve(phi, m1, m2, **kw)
+
+
+def eofa_heatbath(ctx: Context, eta, m1, m2, **kw):
+    return ctx.eofa_heatbath(eta, m1, m2, **kw)
 
 
 def eofa_force(ctx: Context, m1, m2, **kw):

@@ -55,6 +55,11 @@ hipError_t launch_dev_to_nat5(void* nat, const void* de, const void* dodd, const
                               size_t N, hipStream_t st);
 hipError_t launch_eofa_source(const void* phi, const double* om, void* bLe, void* bLo, void* bRe,
                               void* bRo, const int L[4], int Ls, size_t N, hipStream_t st);
+hipError_t launch_hb_init(const void* eta, void* phi, double c0, size_t n, hipStream_t st);
+hipError_t launch_hb_accum(void* phi, const void* ce, const void* co, const double* om, double coef,
+                           int lower, const int L[4], int Ls, size_t N, hipStream_t st);
+void zolotarev_inv_sqrt(double lo, double hi, int n, double* alpha0, double* alpha, double* beta,
+                        double* delta_out);
 int action_blocks(int V);
 hipError_t launch_eofa_action(const void* phi, const void* chiL, const void* chiR, const double* om,
                               double k, void* Mphi, double* partial, int V, int Ls, hipStream_t st);
@@ -777,6 +782,85 @@ int solve_impl(eofa_ctx* c, double m1, double m2, const void* phi, const void* x
     return status;
 }
 
+// Heatbath of eq. (3.1).  With gamma_l = 1/(1 + beta_l) and h(m) = m / N(m),
+//   H(m1) - g Delta_- P_- = H(m+ = m1, m- = mL),  h(mL) = h(m1) + g (h(m2) - h(m1)),
+//   H(m2) - g Delta_+ P_+ = H(m+ = mR, m- = m2),  h(mR) = h(m2) + g (h(m1) - h(m2)),
+// for g = gamma_l (L side) and g = gamma_l beta_l (R side): every shifted
+// operator is an ordinary H(m+, m-), solved in the Cayley form like eofa_solve.
+int heatbath_impl(eofa_ctx* c, double m1, double m2, const void* eta, int n, double a0,
+                  const double* al, const double* be, void* phi, const eofa_solver_t* sp,
+                  eofa_stats_t* stats) {
+    if (!c || !eta || !phi) fail(EOFA_EINVAL, "NULL argument");
+    if (eta == phi) fail(EOFA_EINVAL, "eta and phi may not alias");
+    if (n < 0 || n > 64) fail(EOFA_EINVAL, "n_poles must be in [0, 64]");
+    if (n > 0 && (!al || !be)) fail(EOFA_EINVAL, "NULL rational coefficients");
+    validate_solver(sp);
+    if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
+    if (!std::isfinite(a0)) fail(EOFA_EINVAL, "alpha0 must be finite");
+    double k;
+    omega_k(c, m1, m2, &k);
+    const double bL = std::pow(c->b5, c->Ls), cL = std::pow(-c->c5, c->Ls);
+    auto h = [&](double m) { return m / (bL + m * cL); };
+    // h^-1(y) = y b5^Ls / (1 - y (-c5)^Ls); N(h^-1(y)) = b5^Ls / (1 - y (-c5)^Ls) > 0
+    auto hinv = [&](double y) {
+        const double d = 1.0 - y * cL;
+        if (!(d > 0)) fail(EOFA_EINVAL, "a pole shift gives N(m) <= 0");
+        return y * bL / d;
+    };
+    std::vector<double> mL(n), mR(n);
+    double c0 = a0;
+    for (int l = 0; l < n; ++l) {
+        if (!(be[l] > -1.0) || !std::isfinite(be[l]) || !std::isfinite(al[l]))
+            fail(EOFA_EINVAL, "rational coefficients must be finite with beta_l > -1");
+        const double g = 1.0 / (1.0 + be[l]);
+        mL[l] = hinv(h(m1) + g * (h(m2) - h(m1)));
+        mR[l] = hinv(h(m2) + g * be[l] * (h(m1) - h(m2)));
+        c0 += al[l] * g;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const double f0 = c->flops;
+    if (stats) *stats = eofa_stats_t{};
+    hipchk(launch_hb_init(eta, phi, c0, (size_t)c->V * 12, c->st), "heatbath");
+    int status = EOFA_OK;
+    if (k != 0.0 && n > 0) {
+        Half& bLe = ws(c, "bL_e", P64);
+        Half& bLo = ws(c, "bL_o", P64);
+        Half& bRe = ws(c, "bR_e", P64);
+        Half& bRo = ws(c, "bR_o", P64);
+        hipchk(launch_eofa_source(eta, c->om, bLe.d, bLo.d, bRe.d, bRo.d, c->L, c->Ls, c->N, c->st),
+               "source");
+        Half& ye = ws(c, "y_e", P64);
+        Half& yo = ws(c, "y_o", P64);
+        Half& ce = ws(c, "chi_e", P64);
+        Half& co = ws(c, "chi_o", P64);
+        for (int l = 0; l < n; ++l) {
+            const double g = 1.0 / (1.0 + be[l]);
+            for (int sys = 0; sys < 2; ++sys) {
+                const double mp = sys ? mR[l] : m1, mm = sys ? m2 : mL[l];
+                CayleyOut o = solve_cayley(c, mp, mm, sys ? bRe : bLe, sys ? bRo : bLo, ye, yo, false,
+                                           ce, co, *sp);
+                // + k g P_- Omega_-^dag y_L,  - k g P_+ Omega_+^dag y_R, weighted by alpha_l g
+                const double coef = (sys ? -1.0 : 1.0) * al[l] * g * g * k;
+                hipchk(launch_hb_accum(phi, ce.d, co.d, c->om, coef, sys == 0, c->L, c->Ls, c->N, c->st),
+                       "heatbath");
+                if (stats) {
+                    stats->iters[sys] += o.iters;
+                    stats->reliable_updates[sys] += o.reliable;
+                    stats->true_resid[sys] = std::max(stats->true_resid[sys], o.true_resid);
+                }
+                if (!o.converged) status = EOFA_ENOCONV;
+            }
+        }
+    }
+    hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    if (stats) {
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->flops = c->flops - f0;
+    }
+    if (status != EOFA_OK) g_err = "a heatbath solve did not reach the requested true residual";
+    return status;
+}
+
 template <typename F>
 int guarded(F&& f) {
     try {
@@ -1079,6 +1163,24 @@ int eofa_solve(eofa_ctx_t* c, double m1, double m2, const void* phi, const void*
                void* chiL, void* chiR, void* Mphi, double* S, const eofa_solver_t* sp,
                eofa_stats_t* stats) {
     return guarded([&]() -> int { return solve_impl(c, m1, m2, phi, x0L, x0R, chiL, chiR, Mphi, S, sp, stats); });
+}
+
+int eofa_rational_inv_sqrt(double lo, double hi, int n, double* alpha0, double* alpha, double* beta,
+                           double* delta_out) {
+    return guarded([&] {
+        if (!(lo > 0) || !(hi >= lo) || !std::isfinite(hi))
+            fail(EOFA_EINVAL, "the interval must satisfy 0 < lo <= hi < inf");
+        if (n < 1 || n > 64) fail(EOFA_EINVAL, "n must be in [1, 64]");
+        if (!alpha0 || !alpha || !beta) fail(EOFA_EINVAL, "NULL argument");
+        zolotarev_inv_sqrt(lo, hi, n, alpha0, alpha, beta, delta_out);
+        return EOFA_OK;
+    });
+}
+
+int eofa_heatbath(eofa_ctx_t* c, double m1, double m2, const void* eta, int n_poles, double alpha0,
+                  const double* alpha, const double* beta, void* phi, const eofa_solver_t* sp,
+                  eofa_stats_t* stats) {
+    return guarded([&] { return heatbath_impl(c, m1, m2, eta, n_poles, alpha0, alpha, beta, phi, sp, stats); });
 }
 
 int eofa_force(eofa_ctx_t* c, double m1, double m2, const void* phi, const void* chiL, const void* chiR,

@@ -225,6 +225,63 @@ hipError_t launch_eofa_source(const void* phi, const double* om, void* bLe, void
     return hipGetLastError();
 }
 
+// Heatbath of eq. (3.1).  phi = c0 eta over the 4D field (n complex numbers).
+__global__ void k_hb_init(const double2* __restrict__ eta, double2* __restrict__ phi, double c0,
+                          size_t n) {
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double2 e = eta[t];
+    phi[t] = make_double2(c0 * e.x, c0 * e.y);
+}
+
+// phi(x) += coef P Omega^dag chi(x) = coef sum_s Omega(s) P chi(x, s), with chi
+// a solution in the device layout (parity halves ce/co, component-major).
+// lower: P_- (spins 2, 3) with Omega_-(s) = om[s]; else P_+ (spins 0, 1)
+// with Omega_+(s) = om[Ls - 1 - s].  One work-item per 4D site.
+__global__ void k_hb_accum(double2* __restrict__ phi, const double2* __restrict__ ce,
+                           const double2* __restrict__ co, const double* __restrict__ om,
+                           double coef, int lower, Geo g, size_t N) {
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (t >= 2 * (size_t)g.Vh) return;
+    const int p = (int)(t / g.Vh);
+    const int cb = (int)(t - (size_t)p * g.Vh);
+    int c[4];
+    const int i = natural_site(g, p, cb, c);
+    const double2* src = p ? co : ce;
+    const int k0 = lower ? 6 : 0;
+    double2 acc[6];
+    for (int q = 0; q < 6; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int s = 0; s < g.Ls; ++s) {
+        const double w = lower ? om[s] : om[g.Ls - 1 - s];
+        const size_t r = (size_t)cb * g.Ls + s;
+        for (int q = 0; q < 6; ++q) {
+            const double2 v = src[(size_t)(k0 + q) * N + r];
+            acc[q].x += w * v.x;
+            acc[q].y += w * v.y;
+        }
+    }
+    double2* f = phi + (size_t)i * 12 + k0;
+    for (int q = 0; q < 6; ++q) {
+        const double2 o = f[q];
+        f[q] = make_double2(o.x + coef * acc[q].x, o.y + coef * acc[q].y);
+    }
+}
+
+hipError_t launch_hb_init(const void* eta, void* phi, double c0, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_hb_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (const double2*)eta, (double2*)phi, c0, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_hb_accum(void* phi, const void* ce, const void* co, const double* om, double coef,
+                           int lower, const int L[4], int Ls, size_t N, hipStream_t st) {
+    Geo g = make_geo(L, Ls);
+    const size_t n = 2 * (size_t)g.Vh;
+    hipLaunchKernelGGL(k_hb_accum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (double2*)phi, (const double2*)ce, (const double2*)co, om, coef, lower, g, N);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauge_c16(const void* in, void* out, int Vh, int bf, hipStream_t st) {
     const int n = 2 * 8 * Vh;
     hipLaunchKernelGGL(k_gauge_c16, dim3((n + 255) / 256), dim3(256), 0, st, (const double2*)in, (uint32_t*)out, Vh,

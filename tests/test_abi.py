@@ -64,7 +64,34 @@ def test_null_arguments_are_rejected():
     assert lib.eofa_force(None, 0.1, 0.2, None, None, None, None, None, C.byref(sp),
                           None) == _lib.EOFA_EINVAL
     assert lib.eofa_md_update(None, None, None, None, 0.0, 0.0, None) == _lib.EOFA_EINVAL
+    assert lib.eofa_heatbath(None, 0.1, 0.2, None, 0, 1.0, None, None, None, C.byref(sp),
+                             None) == _lib.EOFA_EINVAL
     lib.eofa_ctx_destroy(None)
+
+
+@pytest.mark.parametrize("lo,hi,n", [(0.5, 5.0, 3), (0.9, 2.7, 4), (1.0, 100.0, 6), (0.05, 50.0, 10),
+                                     (2.0, 2.0, 2), (1e-3, 10.0, 20)])
+def test_rational_coefficients_match_the_oracle(lo, hi, n):
+    """The library's Zolotarev coefficients (host code, elliptic functions by
+    the AGM) against the oracle's (scipy's elliptic functions); the oracle's
+    are pinned by the alternation theorem."""
+    import numpy as np
+    import oracle
+    from paper_1611_00298_amd import rational_inv_sqrt
+    a0, a, b, delta = rational_inv_sqrt(lo, hi, n)
+    o0, oa, ob, od = oracle.zolotarev_inv_sqrt(lo, hi, n)
+    assert a0 == pytest.approx(o0, rel=1e-12)
+    assert np.allclose(a, oa, rtol=1e-12, atol=0) and np.allclose(b, ob, rtol=1e-12, atol=0)
+    assert delta == pytest.approx(od, rel=1e-6, abs=1e-13)
+
+
+@pytest.mark.parametrize("lo,hi,n", [(0.0, 1.0, 2), (-1.0, 1.0, 2), (2.0, 1.0, 2), (1.0, float("inf"), 2),
+                                     (1.0, 2.0, 0), (1.0, 2.0, 65)])
+def test_rational_bad_arguments(lo, hi, n):
+    from paper_1611_00298_amd import _lib, rational_inv_sqrt
+    with pytest.raises(_lib.EOFAError) as e:
+        rational_inv_sqrt(lo, hi, n)
+    assert e.value.code == _lib.EOFA_EINVAL
 
 
 def test_product_path_does_not_touch_the_oracle():
