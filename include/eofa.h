@@ -155,6 +155,22 @@ int eofa_heatbath(eofa_ctx_t *ctx, double m1, double m2, const void *eta_dev, in
                   double alpha0, const double *alpha, const double *beta, void *phi_dev,
                   const eofa_solver_t *solver, eofa_stats_t *stats);
 
+/* Extreme eigenvalues of M_EOFA (eq. (2.5)), for choosing the interval of
+ * the rational heatbath (Section 3.1): n_iter Lanczos steps from start_dev
+ * (4D device field, natural layout; any nonzero vector), each applying
+ * M_EOFA once, i.e. two Cayley-form solves with `solver` as in eofa_solve.
+ *   theta_out[2]: the smallest and largest Ritz values;
+ *   resid_out[2] (NULL: skip): their residual norms |M y - theta y| for the
+ *   unit Ritz vectors y; an eigenvalue of M_EOFA lies within that distance
+ *   of each Ritz value, and every Ritz value lies inside the spectrum (up
+ *   to the solves' tolerance).
+ *   stats (NULL: skip): solve iterations summed over the steps per side.
+ * Requires m1 <= m2 and 2 <= n_iter <= 200.  Workspace: three 4D fields.
+ * EOFA_ENOCONV if a solve missed the tolerance (outputs still written). */
+int eofa_meofa_bounds(eofa_ctx_t *ctx, double m1, double m2, const void *start_dev, int n_iter,
+                      const eofa_solver_t *solver, double *theta_out, double *resid_out,
+                      eofa_stats_t *stats);
+
 /* Pseudofermion force of eq. (3.2):
  *   d^a_{x,mu} S = k chi_L^dag g5 R5 (d^a D_w) chi_L - k chi_R^dag g5 R5 (d^a D_w) chi_R,
  * d^a the derivative along U_mu(x) -> exp(i eps T^a) U_mu(x), T^a = lambda^a/2.

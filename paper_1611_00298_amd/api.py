@@ -161,6 +161,23 @@ class Context:
         d["delta"] = delta
         return phi, d
 
+    # -- eofa_meofa_bounds -----------------------------------------------------
+    def meofa_bounds(self, start, m1, m2, n_iter=20, tol=1e-8, maxiter=20000, inner="fp16",
+                     reliable_delta=0.3, allow_noconv=False):
+        """Extreme eigenvalues of M_EOFA by Lanczos from `start` (4D).
+        Returns (theta_min, theta_max, resid_min, resid_max, stats dict)."""
+        _want(start, self.shape_phi, "start")
+        th = (C.c_double * 2)()
+        rs = (C.c_double * 2)()
+        sp = make_solver(tol, maxiter, inner, reliable_delta)
+        st = Stats()
+        rc = self.lib.eofa_meofa_bounds(self.handle, float(m1), float(m2), _ptr(start), int(n_iter),
+                                        C.byref(sp), th, rs, C.byref(st))
+        check(rc, allow_noconv)
+        d = st.as_dict()
+        d["converged"] = rc == _lib.EOFA_OK
+        return th[0], th[1], rs[0], rs[1], d
+
     # -- eofa_force ------------------------------------------------------------
     def eofa_force(self, m1, m2, phi=None, chiL=None, chiR=None, want_grad=False, tol=1e-10,
                    maxiter=20000, inner="fp64", reliable_delta=0.3):

@@ -60,6 +60,10 @@ hipError_t launch_hb_accum(void* phi, const void* ce, const void* co, const doub
                            int lower, const int L[4], int Ls, size_t N, hipStream_t st);
 void zolotarev_inv_sqrt(double lo, double hi, int n, double* alpha0, double* alpha, double* beta,
                         double* delta_out);
+int dot4_blocks(int V);
+hipError_t launch_dot4(const void* a, const void* b, double* partial, int V, hipStream_t st);
+hipError_t launch_lanczos_axpy(void* w, const void* v, const void* vp, double alpha, double beta,
+                               size_t n, hipStream_t st);
 int action_blocks(int V);
 hipError_t launch_eofa_action(const void* phi, const void* chiL, const void* chiR, const double* om,
                               double k, void* Mphi, double* partial, int V, int Ls, hipStream_t st);
@@ -861,6 +865,151 @@ int heatbath_impl(eofa_ctx* c, double m1, double m2, const void* eta, int n, dou
     return status;
 }
 
+// out = M_EOFA v (eq. (2.5)) for a 4D device field v:
+//   M_EOFA v = v - k P_- Omega_-^dag chi_L + k P_+ Omega_+^dag chi_R,
+// chi_L = H(m1, m1)^-1 Omega_- P_- v, chi_R = H(m1, m2)^-1 Omega_+ P_+ v (Cayley form).
+bool apply_meofa(eofa_ctx* c, double m1, double m2, double k, const void* v, void* out,
+                 const eofa_solver_t& sp, eofa_stats_t* stats) {
+    Half& bLe = ws(c, "bL_e", P64);
+    Half& bLo = ws(c, "bL_o", P64);
+    Half& bRe = ws(c, "bR_e", P64);
+    Half& bRo = ws(c, "bR_o", P64);
+    hipchk(launch_eofa_source(v, c->om, bLe.d, bLo.d, bRe.d, bRo.d, c->L, c->Ls, c->N, c->st), "source");
+    hipchk(launch_hb_init(v, out, 1.0, (size_t)c->V * 12, c->st), "meofa");
+    Half& ye = ws(c, "y_e", P64);
+    Half& yo = ws(c, "y_o", P64);
+    Half& ce = ws(c, "chi_e", P64);
+    Half& co = ws(c, "chi_o", P64);
+    bool ok = true;
+    for (int sys = 0; sys < 2; ++sys) {
+        CayleyOut o = solve_cayley(c, m1, sys ? m2 : m1, sys ? bRe : bLe, sys ? bRo : bLo, ye, yo, false,
+                                   ce, co, sp);
+        hipchk(launch_hb_accum(out, ce.d, co.d, c->om, sys ? k : -k, sys == 0, c->L, c->Ls, c->N, c->st),
+               "meofa");
+        if (stats) {
+            stats->iters[sys] += o.iters;
+            stats->reliable_updates[sys] += o.reliable;
+            stats->true_resid[sys] = std::max(stats->true_resid[sys], o.true_resid);
+        }
+        ok = ok && o.converged;
+    }
+    return ok;
+}
+
+// Eigenvalues and eigenvectors of a small symmetric matrix A (n x n, row
+// major, overwritten) by cyclic Jacobi rotations; Z receives the
+// eigenvectors as columns.
+void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& Z) {
+    Z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double a = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += a;
+                if (i != j) off += a;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double th = (A[(size_t)q * n + q] - A[(size_t)p * n + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int r = 0; r < n; ++r) {   // A <- A J (columns p, q)
+                    const double x = A[(size_t)r * n + p], y = A[(size_t)r * n + q];
+                    A[(size_t)r * n + p] = cs * x - sn * y;
+                    A[(size_t)r * n + q] = sn * x + cs * y;
+                }
+                for (int r = 0; r < n; ++r) {   // A <- J^T A (rows p, q)
+                    const double x = A[(size_t)p * n + r], y = A[(size_t)q * n + r];
+                    A[(size_t)p * n + r] = cs * x - sn * y;
+                    A[(size_t)q * n + r] = sn * x + cs * y;
+                }
+                for (int r = 0; r < n; ++r) {   // Z <- Z J
+                    const double x = Z[(size_t)r * n + p], y = Z[(size_t)r * n + q];
+                    Z[(size_t)r * n + p] = cs * x - sn * y;
+                    Z[(size_t)r * n + q] = sn * x + cs * y;
+                }
+            }
+    }
+}
+
+// Lanczos on M_EOFA (Hermitian positive definite, Section 2) from `start`:
+// the extreme Ritz values of the tridiagonal T_j and their residual norms
+// beta_j |s_j| (s_j the last component of the Ritz vector), for choosing the
+// interval of the rational heatbath of Section 3.1.
+int bounds_impl(eofa_ctx* c, double m1, double m2, const void* start, int n_iter, const eofa_solver_t* sp,
+                double* theta, double* resid, eofa_stats_t* stats) {
+    if (!c || !start || !theta) fail(EOFA_EINVAL, "NULL argument");
+    if (n_iter < 2 || n_iter > 200) fail(EOFA_EINVAL, "n_iter must be in [2, 200]");
+    validate_solver(sp);
+    if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
+    double k;
+    omega_k(c, m1, m2, &k);
+    const auto t0 = std::chrono::steady_clock::now();
+    const double f0 = c->flops;
+    if (stats) *stats = eofa_stats_t{};
+    const size_t n = (size_t)c->V * 12;
+    const size_t bytes = n * 16;
+    void* vb[3] = {rawbuf(c, "lz0", bytes), rawbuf(c, "lz1", bytes), rawbuf(c, "lz2", bytes)};
+    const int nb = dot4_blocks(c->V);
+    auto dot = [&](const void* a, const void* b) {
+        hipchk(launch_dot4(a, b, c->partial, c->V, c->st), "dot");
+        reduce(c, nb, S_T0);
+        const double r = read_slot(c, S_T0);
+        check_finite(r, "Lanczos inner product");
+        return r;
+    };
+    const double s2 = dot(start, start);
+    if (!(s2 > 0)) fail(EOFA_EINVAL, "the start vector is zero");
+    void* vp = vb[0];
+    void* v = vb[1];
+    void* w = vb[2];
+    hipchk(launch_hb_init(start, v, 1.0 / std::sqrt(s2), n, c->st), "scale");
+    std::vector<double> al, be;
+    int status = EOFA_OK;
+    for (int j = 0; j < n_iter; ++j) {
+        if (!apply_meofa(c, m1, m2, k, v, w, *sp, stats)) status = EOFA_ENOCONV;
+        const double a = dot(v, w);
+        const double b = be.empty() ? 0.0 : be.back();
+        hipchk(launch_lanczos_axpy(w, v, be.empty() ? nullptr : vp, a, b, n, c->st), "lanczos");
+        al.push_back(a);
+        const double bn = std::sqrt(std::max(dot(w, w), 0.0));
+        be.push_back(bn);
+        if (bn <= 1e-14 * std::fabs(a)) break;   // invariant subspace: T is exact
+        hipchk(launch_hb_init(w, vp, 1.0 / bn, n, c->st), "scale");   // v_{j+1} into the old v_{j-1}
+        std::swap(vp, v);                                               // vp = v_j, v = v_{j+1}
+    }
+    const int m = (int)al.size();
+    std::vector<double> T((size_t)m * m, 0.0), Z;
+    for (int i = 0; i < m; ++i) {
+        T[(size_t)i * m + i] = al[i];
+        if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = be[i];
+    }
+    jacobi_eigen(m, T, Z);
+    int imin = 0, imax = 0;
+    for (int i = 1; i < m; ++i) {
+        if (T[(size_t)i * m + i] < T[(size_t)imin * m + imin]) imin = i;
+        if (T[(size_t)i * m + i] > T[(size_t)imax * m + imax]) imax = i;
+    }
+    theta[0] = T[(size_t)imin * m + imin];
+    theta[1] = T[(size_t)imax * m + imax];
+    if (resid) {
+        resid[0] = be[m - 1] * std::fabs(Z[(size_t)(m - 1) * m + imin]);
+        resid[1] = be[m - 1] * std::fabs(Z[(size_t)(m - 1) * m + imax]);
+    }
+    hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    if (stats) {
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->flops = c->flops - f0;
+    }
+    if (status != EOFA_OK) g_err = "an M_EOFA solve did not reach the requested true residual";
+    return status;
+}
+
 template <typename F>
 int guarded(F&& f) {
     try {
@@ -1181,6 +1330,11 @@ int eofa_heatbath(eofa_ctx_t* c, double m1, double m2, const void* eta, int n_po
                   const double* alpha, const double* beta, void* phi, const eofa_solver_t* sp,
                   eofa_stats_t* stats) {
     return guarded([&] { return heatbath_impl(c, m1, m2, eta, n_poles, alpha0, alpha, beta, phi, sp, stats); });
+}
+
+int eofa_meofa_bounds(eofa_ctx_t* c, double m1, double m2, const void* start, int n_iter,
+                      const eofa_solver_t* sp, double* theta_out, double* resid_out, eofa_stats_t* stats) {
+    return guarded([&] { return bounds_impl(c, m1, m2, start, n_iter, sp, theta_out, resid_out, stats); });
 }
 
 int eofa_force(eofa_ctx_t* c, double m1, double m2, const void* phi, const void* chiL, const void* chiR,

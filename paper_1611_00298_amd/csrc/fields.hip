@@ -267,6 +267,58 @@ __global__ void k_hb_accum(double2* __restrict__ phi, const double2* __restrict_
     }
 }
 
+// Lanczos on M_EOFA (4D fields, 12 complex per site).
+// partial[block] = sum over the block's sites of Re <a, b>.
+__global__ void __launch_bounds__(256) k_dot4(const double2* __restrict__ a,
+                                              const double2* __restrict__ b, double* partial, int V) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0;
+    if (i < V) {
+        for (int q = 0; q < 12; ++q) {
+            const double2 x = a[(size_t)i * 12 + q], y = b[(size_t)i * 12 + q];
+            acc += x.x * y.x + x.y * y.y;
+        }
+    }
+    __shared__ double red[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// w = w - alpha v - beta vp (the three-term recurrence; vp may be NULL when beta = 0)
+__global__ void k_lanczos_axpy(double2* __restrict__ w, const double2* __restrict__ v,
+                               const double2* __restrict__ vp, double alpha, double beta, size_t n) {
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double2 x = w[t];
+    const double2 a = v[t];
+    x.x -= alpha * a.x;
+    x.y -= alpha * a.y;
+    if (vp) {
+        const double2 c = vp[t];
+        x.x -= beta * c.x;
+        x.y -= beta * c.y;
+    }
+    w[t] = x;
+}
+
+int dot4_blocks(int V) { return (V + 255) / 256; }
+
+hipError_t launch_dot4(const void* a, const void* b, double* partial, int V, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot4, dim3(dot4_blocks(V)), dim3(256), 0, st, (const double2*)a,
+                       (const double2*)b, partial, V);
+    return hipGetLastError();
+}
+
+hipError_t launch_lanczos_axpy(void* w, const void* v, const void* vp, double alpha, double beta,
+                               size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lanczos_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       (double2*)w, (const double2*)v, (const double2*)vp, alpha, beta, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_hb_init(const void* eta, void* phi, double c0, size_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_hb_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        (const double2*)eta, (double2*)phi, c0, n);

@@ -1,7 +1,8 @@
 """GPU EOFA heatbath (eq. (3.1)) against the CPU oracle: parity with the
 oracle's heatbath (the shifted operators inverted as written), against the
-exact M_EOFA^(-1/2) on a lattice small enough for dense algebra, and the
-defining property phi^dag M_EOFA phi = eta^dag eta at a larger size."""
+exact M_EOFA^(-1/2) on a lattice small enough for dense algebra, the
+defining property phi^dag M_EOFA phi = eta^dag eta at a larger size, and the
+Lanczos estimate of M_EOFA's spectral interval."""
 import ctypes as C
 
 import numpy as np
@@ -138,3 +139,31 @@ def test_heatbath_errors(c1_heatbath):
         assert rc == _lib.EOFA_EINVAL
         with pytest.raises(ValueError):
             ctx.eofa_heatbath(eta_d, 0.04, 1.0)
+
+
+def test_meofa_bounds_dense():
+    """Lanczos extremes of M_EOFA (eq. (2.5)) against the dense spectrum:
+    Ritz values lie inside it, each residual interval holds an eigenvalue,
+    and enough steps resolve both ends."""
+    from paper_1611_00298_amd import Context
+    lat = oracle.Lattice((2, 2, 2, 4), 4, M5=1.8, alpha=2.0)
+    U = din.random_gauge(lat.L, 0.3, 11)
+    m1, m2 = 0.1, 0.6
+    H1 = dense(lambda v: oracle.H_op(lat, U, m1, m1, v), lat.shape5)
+    H12 = dense(lambda v: oracle.H_op(lat, U, m1, m2, v), lat.shape5)
+    M = build_M_eofa(lat, U, m1, m2, H1, H12)
+    lam = np.linalg.eigvalsh(0.5 * (M + M.conj().T))
+    start = din.gaussian_4d(lat.L, 404)
+    with Context(lat.L, lat.Ls, to_dev(U), M5=1.8, alpha=2.0) as ctx:
+        for n_iter in (6, 60):
+            tmin, tmax, rmin, rmax, st = ctx.meofa_bounds(to_dev(start), m1, m2, n_iter=n_iter, tol=1e-12,
+                                                          inner="fp64")
+            assert st["converged"] and min(st["iters"]) > 0
+            assert lam[0] - 1e-9 <= tmin <= tmax <= lam[-1] + 1e-9
+            assert np.abs(lam - tmin).min() <= rmin + 1e-9
+            assert np.abs(lam - tmax).min() <= rmax + 1e-9
+        # the top of the spectrum is isolated and converges fully; the bottom
+        # (M_L's eigenvalues, clustered near 1) to well within what an
+        # interval for the rational approximation needs
+        assert tmax == pytest.approx(lam[-1], rel=1e-8) and rmax < 1e-6, (tmax, rmax, lam[-3:])
+        assert tmin == pytest.approx(lam[0], rel=1e-3), (tmin, rmin, lam[:3])
