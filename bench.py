@@ -237,6 +237,70 @@ def trajectory(args):
     return 0
 
 
+def heatbath(args):
+    """The EOFA heatbath of eq. (3.1) on the selected workload (default
+    24^3x64, Ls = 24): M_EOFA's spectral interval by Lanczos, Zolotarev's
+    rational approximation with the fewest poles reaching a relative error
+    of 1e-10 on it, then phi = M_EOFA^(-1/2) eta by 2 N_p Cayley-form
+    solves, checked by phi^dag M_EOFA phi = eta^dag eta.  Prints one JSON
+    line."""
+    import numpy as np
+    import torch
+    import dwf_inputs as din
+    from paper_1611_00298_amd import Context, rational_inv_sqrt
+
+    pre = din.preset(args.workload)
+    dev = torch.device("cuda:0")
+    m1, m2 = pre["m1"], pre["m2"]
+    log(f"heatbath: generating {args.workload} inputs")
+    U = torch.from_numpy(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"])).to(dev)
+    eta_h = din.gaussian_4d(pre["L"], pre["seed_phi"])   # P(eta) ~ exp(-eta^dag eta)
+    eta = torch.from_numpy(eta_h).to(dev)
+    ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
+    solver = dict(inner=args.inner, reliable_delta=args.delta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tmin, tmax, rmin, rmax, stb = ctx.meofa_bounds(eta, m1, m2, n_iter=args.lanczos, tol=1e-8, **solver)
+    t_bounds = time.perf_counter() - t0
+    log(f"heatbath: Lanczos ({args.lanczos} steps, {t_bounds:.1f} s): theta [{tmin:.6f}, {tmax:.6f}], "
+        f"residuals {rmin:.2e}, {rmax:.2e}")
+    # Ritz values converge from inside the spectrum: widen by their residuals and 2 %
+    lo, hi = 0.98 * max(tmin - rmin, 0.5 * tmin), 1.02 * (tmax + rmax)
+    n = 1
+    while rational_inv_sqrt(lo, hi, n)[3] > 1e-10:
+        n += 1
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, st = ctx.eofa_heatbath(eta, m1, m2, lo=lo, hi=hi, n_poles=n, tol=1e-10, **solver)
+    torch.cuda.synchronize()
+    t_hb = time.perf_counter() - t0
+    hq = ctx.timing_query("hop")
+    ctx.timing_enable(False)
+    log(f"heatbath: {n} poles, {2 * n} solves, {t_hb:.1f} s, iterations {st['iters']}")
+    _, _, _, S, stc = ctx.eofa_solve(phi, m1, m2, tol=1e-10, want_mphi=False, **solver)
+    ee = float(np.vdot(eta_h, eta_h).real)
+    ctx.close()
+    out = {"metric": "EOFA heatbath (eq. 3.1): time for phi = M_EOFA^-1/2 eta (1 GPU)",
+           "value": t_hb, "unit": "s", "higher_is_better": False,
+           "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
+                                  f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}",
+                      "inner_precision": args.inner, "tol": 1e-10},
+           "data": "synthetic (random SU(3) links exp(i eps H), Gaussian eta)",
+           "spectrum": {"lanczos_steps": args.lanczos, "theta": [tmin, tmax], "resid": [rmin, rmax],
+                        "seconds": t_bounds, "iters": stb["iters"]},
+           "rational": {"interval": [lo, hi], "n_poles": n, "delta": st["delta"]},
+           "heatbath": {"seconds": t_hb, "solves": 2 * n, "iters": st["iters"],
+                        "reliable_updates": st["reliable_updates"], "true_resid": st["true_resid"]},
+           "hop": {"launches": hq["count"], "avg_ms": hq["ms"] / max(hq["count"], 1),
+                   "achieved_GBs": hq["bytes"] / max(hq["ms"], 1e-30) / 1e6,
+                   "time_share": hq["ms"] / 1e3 / t_hb},
+           "check": {"S_over_eta2_minus_1": S / ee - 1.0, "bound_2delta": 2 * st["delta"],
+                     "solve_iters": stc["iters"]}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +315,10 @@ def main():
     ap.add_argument("--trajectory", action="store_true",
                     help="instead of the step benchmark: the 24^3x64 fermion-only trajectory workload (c5), "
                          "mixed vs FP64 dH and reversibility")
+    ap.add_argument("--heatbath", action="store_true",
+                    help="instead of the step benchmark: the EOFA heatbath of eq. (3.1) (Lanczos interval, "
+                         "Zolotarev poles, 2 N_p solves) on the selected workload")
+    ap.add_argument("--lanczos", type=int, default=16, help="Lanczos steps for the heatbath interval")
     ap.add_argument("--dslash", action="store_true",
                     help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -263,6 +331,8 @@ def main():
 
     if args.trajectory:
         return trajectory(args)
+    if args.heatbath:
+        return heatbath(args)
     if args.dslash:
         return dslash(args)
 
