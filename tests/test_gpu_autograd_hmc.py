@@ -97,3 +97,63 @@ def test_mixed_precision_trajectory_against_fp64(c1):
     assert abs(dH16 - dH64) < 1e-6
     assert np.abs(U16.cpu().numpy() - U64.cpu().numpy()).max() < 1e-8
     ctx.update_gauge(to_dev(U0))
+
+
+def test_force_gradient_dt4_scaling_and_reversibility(c1):
+    """The force-gradient QPQPQ integrator (Section 4's integrator family):
+    the energy violation falls like dt^4, it beats leapfrog at the same step,
+    and it is reversible."""
+    from paper_1611_00298_amd.hmc import force_gradient, hamiltonian
+    lat, U0, phi, ctx = c1
+    P0 = din.gaussian_momenta(C1["L"], 307)
+    ph = to_dev(phi)
+
+    def run(n, dt):
+        U, P = to_dev(U0), to_dev(P0)
+        H0, _, _, _ = hamiltonian(ctx, U, P, ph, C1["m1"], C1["m2"], tol=1e-12)
+        st = force_gradient(ctx, U, P, ph, C1["m1"], C1["m2"], n, dt, tol=1e-12)
+        H1, _, _, _ = hamiltonian(ctx, U, P, ph, C1["m1"], C1["m2"], tol=1e-12)
+        assert len(st) == 4 * n
+        return U, P, H1 - H0
+
+    # trajectory length 0.4 (at 0.8 these synthetic fields leave the asymptotic range at dt = 0.2)
+    _, _, dH1 = run(2, 0.2)
+    _, _, dH2 = run(4, 0.1)
+    _, _, dH_lf = run_trajectory(ctx, U0, P0, phi, 4, 0.1, tol=1e-12)
+    assert abs(dH2) > 1e-6, (dH1, dH2)
+    assert 9.0 < abs(dH1 / dH2) < 28.0, (dH1, dH2)
+    assert abs(dH2) < 0.02 * abs(dH_lf), (dH2, dH_lf)
+    U, P, _ = run(4, 0.1)
+    P.neg_()
+    force_gradient(ctx, U, P, ph, C1["m1"], C1["m2"], 4, 0.1, tol=1e-12)
+    assert np.abs(U.cpu().numpy() - U0).max() < 1e-10
+    assert np.abs(-P.cpu().numpy() - P0).max() < 1e-9
+    ctx.update_gauge(to_dev(U0))
+
+
+def test_hmc_trajectory_heatbath_metropolis(c1):
+    """A full trajectory: heatbath (eq. (3.1)) gives S(phi) = eta^dag eta up to
+    the approximation error; u = 0 accepts, u > 1 rejects and restores the
+    links and momenta exactly."""
+    from paper_1611_00298_amd.hmc import force_gradient, trajectory
+    lat, U0, phi, ctx = c1
+    eta = din.gaussian_4d(C1["L"], 405)
+    P0 = din.gaussian_momenta(C1["L"], 308)
+    ee = float(np.vdot(eta, eta).real)
+    from paper_1611_00298_amd import rational_inv_sqrt
+    tmin, tmax, rmin, rmax, _ = ctx.meofa_bounds(to_dev(eta), C1["m1"], C1["m2"], n_iter=30, tol=1e-10,
+                                                 inner="fp64")
+    lo, hi = 0.98 * (tmin - rmin), 1.02 * (tmax + rmax)
+    n_poles = next(n for n in range(1, 40) if rational_inv_sqrt(lo, hi, n)[3] < 1e-9)
+    for u, integ in ((0.0, None), (2.0, force_gradient)):
+        U, P = to_dev(U0), to_dev(P0)
+        r = trajectory(ctx, U, P, to_dev(eta), C1["m1"], C1["m2"], 3, 0.1, lo=lo, hi=hi, n_poles=n_poles,
+                       u_accept=u, integrator=integ, tol=1e-11)
+        assert abs(r["S0"] / ee - 1) < 1e-7, (r["S0"], ee, lo, hi, n_poles)
+        assert abs(r["dH"]) < 1.0   # leapfrog at dt = 0.1 on these fields: |dH| ~ 0.05
+        assert r["accepted"] == (u == 0.0)
+        if r["accepted"]:
+            assert np.abs(U.cpu().numpy() - U0).max() > 1e-3
+        else:
+            assert np.array_equal(U.cpu().numpy(), U0) and np.array_equal(P.cpu().numpy(), P0)
+    ctx.update_gauge(to_dev(U0))
