@@ -272,7 +272,8 @@ def heatbath(args):
     ctx.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    phi, st = ctx.eofa_heatbath(eta, m1, m2, lo=lo, hi=hi, n_poles=n, tol=1e-10, **solver)
+    phi, st = ctx.eofa_heatbath(eta, m1, m2, lo=lo, hi=hi, n_poles=n, tol=1e-10, forecast=args.forecast,
+                                **solver)
     torch.cuda.synchronize()
     t_hb = time.perf_counter() - t0
     hq = ctx.timing_query("hop")
@@ -290,7 +291,7 @@ def heatbath(args):
            "spectrum": {"lanczos_steps": args.lanczos, "theta": [tmin, tmax], "resid": [rmin, rmax],
                         "seconds": t_bounds, "iters": stb["iters"]},
            "rational": {"interval": [lo, hi], "n_poles": n, "delta": st["delta"]},
-           "heatbath": {"seconds": t_hb, "solves": 2 * n, "iters": st["iters"],
+           "heatbath": {"seconds": t_hb, "solves": 2 * n, "forecast": args.forecast, "iters": st["iters"],
                         "reliable_updates": st["reliable_updates"], "true_resid": st["true_resid"]},
            "hop": {"launches": hq["count"], "avg_ms": hq["ms"] / max(hq["count"], 1),
                    "achieved_GBs": hq["bytes"] / max(hq["ms"], 1e-30) / 1e6,
@@ -319,6 +320,8 @@ def main():
                     help="instead of the step benchmark: the EOFA heatbath of eq. (3.1) (Lanczos interval, "
                          "Zolotarev poles, 2 N_p solves) on the selected workload")
     ap.add_argument("--lanczos", type=int, default=16, help="Lanczos steps for the heatbath interval")
+    ap.add_argument("--forecast", type=int, default=8,
+                    help="heatbath: earlier solutions per side for chronological initial guesses (0: none)")
     ap.add_argument("--dslash", action="store_true",
                     help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
     ap.add_argument("--copy-calibration", action="store_true",

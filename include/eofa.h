@@ -147,13 +147,18 @@ int eofa_rational_inv_sqrt(double lo, double hi, int n, double *alpha0, double *
  *   pointers, natural layout, may not alias.
  *   alpha/beta: caller-owned host arrays of n_poles doubles, beta_l > -1
  *   (n_poles = 0, or m1 = m2 where k = 0: phi = (alpha0 + sum_l alpha_l gamma_l) eta).
+ *   forecast: chronological initial guesses (Section 5.2): each solve starts
+ *   from the combination of the last `forecast` solutions of the same side
+ *   that minimises its residual (Brower et al.); 0 starts every solve from
+ *   zero.  0 <= forecast <= 16; the context then holds 3 * forecast extra
+ *   FP64 half fields (2 GB each at 24^3x64, Ls = 24).
  *   stats (NULL: skip): iterations and reliable updates summed over the
  *   poles for the L (index 0) and R (index 1) side, true_resid the largest.
  * Requires m1 <= m2.  EOFA_ENOCONV if a solve missed the tolerance (phi is
  * still written); EOFA_EINVAL for bad arguments or a shift with N(m) <= 0. */
 int eofa_heatbath(eofa_ctx_t *ctx, double m1, double m2, const void *eta_dev, int n_poles,
-                  double alpha0, const double *alpha, const double *beta, void *phi_dev,
-                  const eofa_solver_t *solver, eofa_stats_t *stats);
+                  double alpha0, const double *alpha, const double *beta, int forecast,
+                  void *phi_dev, const eofa_solver_t *solver, eofa_stats_t *stats);
 
 /* Extreme eigenvalues of M_EOFA (eq. (2.5)), for choosing the interval of
  * the rational heatbath (Section 3.1): n_iter Lanczos steps from start_dev

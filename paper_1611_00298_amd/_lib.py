@@ -69,7 +69,7 @@ def load() -> C.CDLL:
         "eofa_md_update": (I_, [P, P, P, P, D, D, C.POINTER(C.c_double)]),
         "eofa_rational_inv_sqrt": (I_, [D, D, I_, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
-        "eofa_heatbath": (I_, [P, D, D, P, I_, D, C.POINTER(C.c_double), C.POINTER(C.c_double), P,
+        "eofa_heatbath": (I_, [P, D, D, P, I_, D, C.POINTER(C.c_double), C.POINTER(C.c_double), I_, P,
                                C.POINTER(Solver), C.POINTER(Stats)]),
         "eofa_meofa_bounds": (I_, [P, D, D, P, I_, C.POINTER(Solver), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(Stats)]),

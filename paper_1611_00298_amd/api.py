@@ -131,9 +131,11 @@ class Context:
 
     # -- eofa_heatbath ---------------------------------------------------------
     def eofa_heatbath(self, eta, m1, m2, coeffs=None, lo=None, hi=None, n_poles=None, tol=1e-10,
-                      maxiter=20000, inner="fp64", reliable_delta=0.3, allow_noconv=False):
+                      maxiter=20000, inner="fp64", reliable_delta=0.3, forecast=8, allow_noconv=False):
         """phi ~ M_EOFA^(-1/2) eta (eq. (3.1)).  The rational approximation is
         either coeffs = (a0, a, b) or Zolotarev's on [lo, hi] with n_poles.
+        forecast: earlier solutions per side used for chronological initial
+        guesses (Section 5.2; 0: start from zero).
         Returns (phi, stats dict); stats carries the approximation error
         "delta" when the coefficients were computed here."""
         _want(eta, self.shape_phi, "eta")
@@ -154,7 +156,7 @@ class Context:
         sp = make_solver(tol, maxiter, inner, reliable_delta)
         st = Stats()
         rc = self.lib.eofa_heatbath(self.handle, float(m1), float(m2), _ptr(eta), n, float(a0), ca, cb,
-                                    _ptr(phi), C.byref(sp), C.byref(st))
+                                    int(forecast), _ptr(phi), C.byref(sp), C.byref(st))
         check(rc, allow_noconv)
         d = st.as_dict()
         d["converged"] = rc == _lib.EOFA_OK

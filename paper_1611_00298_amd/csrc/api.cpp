@@ -61,6 +61,10 @@ hipError_t launch_hb_accum(void* phi, const void* ce, const void* co, const doub
 void zolotarev_inv_sqrt(double lo, double hi, int n, double* alpha0, double* alpha, double* beta,
                         double* delta_out);
 int dot4_blocks(int V);
+hipError_t launch_cdot64(const void* a, const void* b, size_t n5, size_t N, double* partial, int nblk,
+                         hipStream_t st);
+hipError_t launch_caxpy64(void* x, const void* y, double cr, double ci, size_t n5, size_t N, int nblk,
+                          hipStream_t st);
 hipError_t launch_dot4(const void* a, const void* b, double* partial, int V, hipStream_t st);
 hipError_t launch_lanczos_axpy(void* w, const void* v, const void* vp, double alpha, double beta,
                                size_t n, hipStream_t st);
@@ -650,10 +654,84 @@ struct CayleyOut {
     bool converged = false;
 };
 
+void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& Z);
+
+// Earlier odd-site solutions y_i (FP64) and room for Mhat y_i, for the
+// chronological initial guess of Section 5.2.
+struct Forecast {
+    Half* const* y;
+    Half* const* w;
+    int k;
+};
+
+// <a, b> over FP64 half fields (deterministic two-stage reduction)
+void cdot64(eofa_ctx* c, const Half& a, const Half& b, double* re, double* im) {
+    const int nb = c->nblk_blas;
+    hipchk(launch_cdot64(a.d, b.d, c->n5, c->N, c->partial, nb, c->st), "cdot");
+    hipchk(launch_reduce(c->partial, nb, c->sc, S_T0, c->st), "reduce");
+    hipchk(launch_reduce(c->partial + nb, nb, c->sc, S_T1, c->st), "reduce");
+    const double* v = read_slots(c, S_T0, 2);
+    *re = v[0];
+    *im = v[1];
+    check_finite(*re + *im, "forecast inner product");
+}
+
+// Chronological guess (Brower et al.): yo = sum_i c_i y_i minimising
+// |bhat - Mhat yo| over the span of the earlier solutions, which for CGNR is
+// also the minimum of the Mhat^dag Mhat energy norm of the error.  The
+// normal equations G c = h, G_ij = <Mhat y_i, Mhat y_j>, h_i = <Mhat y_i, bhat>,
+// are solved on the host through the real symmetric form of G with
+// eigenvalues below 1e-12 of the largest dropped (the y_i are close to
+// linearly dependent).
+void forecast_guess(eofa_ctx* c, double mp, double mm, const Half& bhat, const Forecast& f, Half& yo) {
+    const int k = f.k;
+    Half& te = ws(c, "fc_t_e", P64);
+    Half& to = ws(c, "fc_t_o", P64);
+    for (int i = 0; i < k; ++i) {
+        local_op(c, P64, *f.y[i], to, Dt(c, 0), I5, mp, mm);
+        schur_k1(c, P64, to, te, mp, mm);
+        schur_k2(c, P64, te, *f.y[i], *f.w[i], mp, mm, nullptr);
+    }
+    const int n = 2 * k;
+    std::vector<double> A((size_t)n * n), rhs(n), Z;
+    for (int i = 0; i < k; ++i) {
+        for (int j = i; j < k; ++j) {
+            double gr, gi;
+            cdot64(c, *f.w[i], *f.w[j], &gr, &gi);
+            // [[Re G, -Im G], [Im G, Re G]] with G_ji = conj(G_ij)
+            A[(size_t)i * n + j] = A[(size_t)(k + i) * n + (k + j)] = gr;
+            A[(size_t)j * n + i] = A[(size_t)(k + j) * n + (k + i)] = gr;
+            A[(size_t)(k + i) * n + j] = gi;
+            A[(size_t)i * n + (k + j)] = -gi;
+            A[(size_t)(k + j) * n + i] = -gi;
+            A[(size_t)j * n + (k + i)] = gi;
+        }
+        double hr, hi;
+        cdot64(c, *f.w[i], bhat, &hr, &hi);
+        rhs[i] = hr;
+        rhs[k + i] = hi;
+    }
+    jacobi_eigen(n, A, Z);
+    double lmax = 0;
+    for (int j = 0; j < n; ++j) lmax = std::max(lmax, A[(size_t)j * n + j]);
+    std::vector<double> x(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        const double lam = A[(size_t)j * n + j];
+        if (!(lam > 1e-12 * lmax)) continue;
+        double d = 0;
+        for (int r = 0; r < n; ++r) d += Z[(size_t)r * n + j] * rhs[r];
+        for (int r = 0; r < n; ++r) x[r] += Z[(size_t)r * n + j] * d / lam;
+    }
+    zero(c, yo);
+    for (int i = 0; i < k; ++i)
+        hipchk(launch_caxpy64(yo.d, f.y[i]->d, x[i], x[k + i], c->n5, c->N, c->nblk_blas, c->st), "caxpy");
+}
+
 // Solve D_DWF(mp, mm) y = b (even-odd, Section 5.1), then chi = Dtilde y.
 // y_e/y_o hold an initial guess when `guess`.  Writes chi_e/chi_o.
 CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const Half& bo, Half& ye,
-                       Half& yo, bool guess, Half& chie, Half& chio, const eofa_solver_t& sp) {
+                       Half& yo, bool guess, Half& chie, Half& chio, const eofa_solver_t& sp,
+                       const Forecast* fc = nullptr) {
     CayleyOut out;
     const int nb = c->nblk_hop;
     // |b|^2
@@ -678,6 +756,10 @@ CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const 
     const int prec = sp.inner;
     double thresh = 0.5 * sp.tol * bnorm;
     bool have = guess;
+    if (fc && fc->k > 0) {   // chronological guess from earlier solutions (Section 5.2)
+        forecast_guess(c, mp, mm, bhat, *fc, yo);
+        have = true;
+    }
     for (int attempt = 0; attempt < 4; ++attempt) {
         SolveResult r = cgnr_schur(c, mp, mm, bhat, yo, have, thresh, sp.maxiter - out.iters, prec,
                                    sp.reliable_delta > 0 ? sp.reliable_delta : 0.1);
@@ -792,12 +874,13 @@ int solve_impl(eofa_ctx* c, double m1, double m2, const void* phi, const void* x
 // for g = gamma_l (L side) and g = gamma_l beta_l (R side): every shifted
 // operator is an ordinary H(m+, m-), solved in the Cayley form like eofa_solve.
 int heatbath_impl(eofa_ctx* c, double m1, double m2, const void* eta, int n, double a0,
-                  const double* al, const double* be, void* phi, const eofa_solver_t* sp,
+                  const double* al, const double* be, int forecast, void* phi, const eofa_solver_t* sp,
                   eofa_stats_t* stats) {
     if (!c || !eta || !phi) fail(EOFA_EINVAL, "NULL argument");
     if (eta == phi) fail(EOFA_EINVAL, "eta and phi may not alias");
     if (n < 0 || n > 64) fail(EOFA_EINVAL, "n_poles must be in [0, 64]");
     if (n > 0 && (!al || !be)) fail(EOFA_EINVAL, "NULL rational coefficients");
+    if (forecast < 0 || forecast > 16) fail(EOFA_EINVAL, "forecast must be in [0, 16]");
     validate_solver(sp);
     if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
     if (!std::isfinite(a0)) fail(EOFA_EINVAL, "alpha0 must be finite");
@@ -837,12 +920,22 @@ int heatbath_impl(eofa_ctx* c, double m1, double m2, const void* eta, int n, dou
         Half& yo = ws(c, "y_o", P64);
         Half& ce = ws(c, "chi_e", P64);
         Half& co = ws(c, "chi_o", P64);
+        // per side, a ring of the last `forecast` odd-site solutions (Section 5.2)
+        const int K = std::min(forecast, n - 1);
+        std::vector<Half*> ring[2], wv;
+        for (int i = 0; i < K; ++i) {
+            ring[0].push_back(&ws(c, "fc_L" + std::to_string(i), P64));
+            ring[1].push_back(&ws(c, "fc_R" + std::to_string(i), P64));
+            wv.push_back(&ws(c, "fc_W" + std::to_string(i), P64));
+        }
         for (int l = 0; l < n; ++l) {
             const double g = 1.0 / (1.0 + be[l]);
             for (int sys = 0; sys < 2; ++sys) {
                 const double mp = sys ? mR[l] : m1, mm = sys ? m2 : mL[l];
+                const Forecast fc{ring[sys].data(), wv.data(), std::min(l, K)};
                 CayleyOut o = solve_cayley(c, mp, mm, sys ? bRe : bLe, sys ? bRo : bLo, ye, yo, false,
-                                           ce, co, *sp);
+                                           ce, co, *sp, K > 0 ? &fc : nullptr);
+                if (K > 0) convert(c, yo, *ring[sys][l % K]);
                 // + k g P_- Omega_-^dag y_L,  - k g P_+ Omega_+^dag y_R, weighted by alpha_l g
                 const double coef = (sys ? -1.0 : 1.0) * al[l] * g * g * k;
                 hipchk(launch_hb_accum(phi, ce.d, co.d, c->om, coef, sys == 0, c->L, c->Ls, c->N, c->st),
@@ -1199,7 +1292,7 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             size_t np = (size_t)2 * c->nblk_hop;
             np = std::max(np, (size_t)action_blocks(c->V));
             np = std::max(np, (size_t)md_blocks(4 * c->V));
-            np = std::max(np, (size_t)c->nblk_blas);
+            np = std::max(np, (size_t)2 * c->nblk_blas);   // complex inner products
             c->npartial = np;
             hipchk(hipMalloc((void**)&c->partial, sizeof(double) * np), "hipMalloc(partial)");
             hipchk(hipMalloc((void**)&c->sc, sizeof(double) * S_NSLOT), "hipMalloc(scalars)");
@@ -1327,9 +1420,11 @@ int eofa_rational_inv_sqrt(double lo, double hi, int n, double* alpha0, double* 
 }
 
 int eofa_heatbath(eofa_ctx_t* c, double m1, double m2, const void* eta, int n_poles, double alpha0,
-                  const double* alpha, const double* beta, void* phi, const eofa_solver_t* sp,
+                  const double* alpha, const double* beta, int forecast, void* phi, const eofa_solver_t* sp,
                   eofa_stats_t* stats) {
-    return guarded([&] { return heatbath_impl(c, m1, m2, eta, n_poles, alpha0, alpha, beta, phi, sp, stats); });
+    return guarded([&] {
+        return heatbath_impl(c, m1, m2, eta, n_poles, alpha0, alpha, beta, forecast, phi, sp, stats);
+    });
 }
 
 int eofa_meofa_bounds(eofa_ctx_t* c, double m1, double m2, const void* start, int n_iter,

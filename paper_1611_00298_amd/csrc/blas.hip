@@ -159,12 +159,62 @@ __global__ void __launch_bounds__(256) k_zero(void* f, float* fn, size_t n5, siz
         st_spinor<P>(f, fn, N, n, v);
 }
 
+// partial Re <a, b> into partial[block] and Im <a, b> into partial[nblk + block]
+// (FP64 half fields; <a, b> = sum conj(a) b)
+__global__ void __launch_bounds__(256) k_cdot64(const void* a, const void* b, size_t n5, size_t N,
+                                                double* partial) {
+    double re = 0, im = 0;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        double x[24], y[24];
+        ld_spinor<P64>(a, nullptr, N, n, x);
+        ld_spinor<P64>(b, nullptr, N, n, y);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            re += x[2 * k] * y[2 * k] + x[2 * k + 1] * y[2 * k + 1];
+            im += x[2 * k] * y[2 * k + 1] - x[2 * k + 1] * y[2 * k];
+        }
+    }
+    block_store_sum(re, partial + blockIdx.x);
+    __syncthreads();   // block_store_sum's LDS is reused
+    block_store_sum(im, partial + gridDim.x + blockIdx.x);
+}
+
+// x += (cr + i ci) y   (FP64 half fields)
+__global__ void __launch_bounds__(256) k_caxpy64(void* x, const void* y, double cr, double ci, size_t n5,
+                                                 size_t N) {
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        double u[24], v[24];
+        ld_spinor<P64>(x, nullptr, N, n, u);
+        ld_spinor<P64>(y, nullptr, N, n, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            u[2 * k] += cr * v[2 * k] - ci * v[2 * k + 1];
+            u[2 * k + 1] += cr * v[2 * k + 1] + ci * v[2 * k];
+        }
+        st_spinor<P64>(x, nullptr, N, n, u);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers (grid: a fixed number of workgroups, grid-stride loops)
 // ---------------------------------------------------------------------------
 int blas_blocks(size_t n5) {
     size_t b = (n5 + 255) / 256;
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+hipError_t launch_cdot64(const void* a, const void* b, size_t n5, size_t N, double* partial, int nblk,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_cdot64, dim3(nblk), dim3(256), 0, st, a, b, n5, N, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_caxpy64(void* x, const void* y, double cr, double ci, size_t n5, size_t N, int nblk,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_caxpy64, dim3(nblk), dim3(256), 0, st, x, y, cr, ci, n5, N);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* partial, int n, double* out, int slot, hipStream_t st) {

@@ -97,10 +97,15 @@ def test_heatbath_property_c2():
                                     inner="fp16")
         assert st["converged"] and st["delta"] < 1e-8
         _, _, _, S, st2 = ctx.eofa_solve(phi, C2["m1"], C2["m2"], tol=1e-10, inner="fp16", want_mphi=False)
+        # chronological guesses (Section 5.2) against zero guesses: same phi, fewer iterations
+        phi0, st0 = ctx.eofa_heatbath(eta_d, C2["m1"], C2["m2"], lo=0.05, hi=20.0, n_poles=10, tol=1e-10,
+                                      inner="fp16", forecast=0)
     ee = float(np.vdot(eta, eta).real)
     assert abs(S / ee - 1.0) <= 1e-7, (S, ee, st, st2)
     # and phi is not eta: M_EOFA is not the identity here
     assert rel(phi.cpu().numpy(), eta) > 1e-3
+    assert rel(phi.cpu().numpy(), phi0.cpu().numpy()) <= 1e-8
+    assert sum(st["iters"]) < 0.8 * sum(st0["iters"]), (st["iters"], st0["iters"])
 
 
 def test_heatbath_special_cases(c1_heatbath):
@@ -134,9 +139,12 @@ def test_heatbath_errors(c1_heatbath):
         # eta and phi may not alias
         sp = _lib.Solver(1e-10, 100, 0, 0.3)
         ca = (C.c_double * 1)(1.0)
-        rc = ctx.lib.eofa_heatbath(ctx.handle, 0.04, 1.0, C.c_void_p(eta_d.data_ptr()), 1, 0.5, ca, ca,
+        rc = ctx.lib.eofa_heatbath(ctx.handle, 0.04, 1.0, C.c_void_p(eta_d.data_ptr()), 1, 0.5, ca, ca, 0,
                                    C.c_void_p(eta_d.data_ptr()), C.byref(sp), None)
         assert rc == _lib.EOFA_EINVAL
+        with pytest.raises(_lib.EOFAError) as e:
+            ctx.eofa_heatbath(eta_d, 0.04, 1.0, coeffs=(a0, a, b), forecast=17)
+        assert e.value.code == _lib.EOFA_EINVAL
         with pytest.raises(ValueError):
             ctx.eofa_heatbath(eta_d, 0.04, 1.0)
 
