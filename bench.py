@@ -302,6 +302,81 @@ def heatbath(args):
     return 0
 
 
+def hmc(args):
+    """One complete fermion-only EOFA HMC trajectory on the 24^3x64, Ls = 24
+    trajectory workload, timed by phase in the rows of Table 4: M_EOFA's
+    interval (Lanczos) and the heatbath of eq. (3.1) with chronological
+    guesses, the force-gradient QPQPQ integration (args.md_steps steps over
+    unit trajectory length, four force evaluations per step), the final
+    Hamiltonian, and the Metropolis decision.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import dwf_inputs as din
+    from paper_1611_00298_amd import Context, rational_inv_sqrt
+    from paper_1611_00298_amd.hmc import force_gradient, hamiltonian
+
+    pre = din.preset("c5")
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    m1, m2 = pre["m1"], pre["m2"]
+    n, dt = args.md_steps, 1.0 / args.md_steps
+    log("hmc: generating c5 inputs")
+    U = t(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"]))
+    eta_h = din.gaussian_4d(pre["L"], pre["seed_phi"])
+    eta = t(eta_h)
+    P = t(din.gaussian_momenta(pre["L"], pre["seed_mom"]))
+    ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
+    solver = dict(tol=1e-10, inner=args.inner, reliable_delta=args.delta)
+    sync = torch.cuda.synchronize
+    sync()
+    t0 = time.perf_counter()
+    tmin, tmax, rmin, rmax, _ = ctx.meofa_bounds(eta, m1, m2, n_iter=args.lanczos, tol=1e-8, inner=args.inner)
+    lo, hi = 0.98 * max(tmin - rmin, 0.5 * tmin), 1.02 * (tmax + rmax)
+    n_poles = next(k for k in range(1, 65) if rational_inv_sqrt(lo, hi, k)[3] <= 1e-10)
+    sync()
+    t_int = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    phi, hb = ctx.eofa_heatbath(eta, m1, m2, lo=lo, hi=hi, n_poles=n_poles, forecast=args.forecast, **solver)
+    sync()
+    t_hb = time.perf_counter() - t0
+    log(f"hmc: interval [{lo:.4f}, {hi:.3f}] ({t_int:.1f} s), heatbath {n_poles} poles {t_hb:.1f} s")
+    t0 = time.perf_counter()
+    H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+    sync()
+    t_h0 = time.perf_counter() - t0
+    prog = lambda i, st: log(f"hmc: force {i}: iters {st['iters']} solve {st['seconds']:.2f}s")
+    t0 = time.perf_counter()
+    fst = force_gradient(ctx, U, P, phi, m1, m2, n, dt, progress=prog, **solver)
+    sync()
+    t_md = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+    sync()
+    t_h1 = time.perf_counter() - t0
+    ee = float(np.vdot(eta_h, eta_h).real)
+    ctx.close()
+    total = t_int + t_hb + t_h0 + t_md + t_h1
+    dH = H1 - H0
+    out = {"metric": "fermion-only EOFA HMC trajectory: time by phase (Table 4 rows), 1 GPU",
+           "value": total, "unit": "s", "higher_is_better": False,
+           "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
+                                  f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}: heatbath + {n} "
+                                  f"force-gradient QPQPQ steps, tau = 1, solves to 1e-10",
+                      "inner_precision": args.inner},
+           "data": "synthetic (random SU(3) links exp(i eps H), Gaussian eta and momenta)",
+           "phases_s": {"interval_lanczos": t_int, "heatbath": t_hb, "initial_H": t_h0,
+                        "force_gradient_integration": t_md, "final_H": t_h1},
+           "shares": {"heatbath_incl_interval": (t_int + t_hb) / total, "heatbath": t_hb / total,
+                      "force_gradient_integration": t_md / total, "energies": (t_h0 + t_h1) / total},
+           "heatbath": {"n_poles": n_poles, "interval": [lo, hi], "iters": hb["iters"],
+                        "S0_over_eta2_minus_1": S0 / ee - 1.0},
+           "md": {"force_evaluations": len(fst), "solve_iters_total": [sum(s["iters"][0] for s in fst),
+                                                                        sum(s["iters"][1] for s in fst)]},
+           "dH": dH, "H0": H0, "accept_probability": float(min(1.0, np.exp(-dH)))}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +397,10 @@ def main():
     ap.add_argument("--lanczos", type=int, default=16, help="Lanczos steps for the heatbath interval")
     ap.add_argument("--forecast", type=int, default=8,
                     help="heatbath: earlier solutions per side for chronological initial guesses (0: none)")
+    ap.add_argument("--hmc", action="store_true",
+                    help="instead of the step benchmark: one full EOFA HMC trajectory (heatbath, force-gradient "
+                         "integration, energies) on the 24^3x64 trajectory workload, timed by phase")
+    ap.add_argument("--md-steps", type=int, default=12, help="hmc: force-gradient steps per unit trajectory")
     ap.add_argument("--dslash", action="store_true",
                     help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -336,6 +415,8 @@ def main():
         return trajectory(args)
     if args.heatbath:
         return heatbath(args)
+    if args.hmc:
+        return hmc(args)
     if args.dslash:
         return dslash(args)
 

@@ -175,3 +175,23 @@ def test_meofa_bounds_dense():
         # interval for the rational approximation needs
         assert tmax == pytest.approx(lam[-1], rel=1e-8) and rmax < 1e-6, (tmax, rmax, lam[-3:])
         assert tmin == pytest.approx(lam[0], rel=1e-3), (tmin, rmin, lam[:3])
+
+
+# ragged workgroup tails, odd Ls, Shamir (alpha = 1) and periodic time
+HB_SHAPES = [((4, 2, 6, 4), 5, 2.0, True), ((4, 4, 2, 2), 4, 1.0, False), ((2, 4, 2, 6), 6, 4.0, True)]
+
+
+@pytest.mark.parametrize("shape", HB_SHAPES, ids=lambda c: f"L{'x'.join(map(str, c[0]))}_Ls{c[1]}_a{c[2]}")
+def test_heatbath_parity_shapes(shape):
+    from paper_1611_00298_amd import Context
+    L, Ls, alpha, ap = shape
+    m1, m2 = 0.04, 1.0
+    lat = oracle.Lattice(L, Ls, M5=1.8, alpha=alpha, antiperiodic_t=ap)
+    U = din.random_gauge(L, 0.3, 23)
+    eta = din.gaussian_4d(L, 406)
+    a0, a, b, _ = oracle.zolotarev_inv_sqrt(0.5, 5.0, 3)
+    ref, _ = oracle.eofa_heatbath(lat, U, m1, m2, eta, a0, a, b, tol=1e-12)
+    with Context(L, Ls, to_dev(U), M5=1.8, alpha=alpha, antiperiodic_t=ap) as ctx:
+        phi, st = ctx.eofa_heatbath(to_dev(eta), m1, m2, coeffs=(a0, a, b), tol=1e-12)
+    assert st["converged"]
+    assert rel(phi.cpu().numpy(), ref) <= 1e-9
