@@ -260,7 +260,7 @@ def heatbath(args):
     solver = dict(inner=args.inner, reliable_delta=args.delta)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tmin, tmax, rmin, rmax, stb = ctx.meofa_bounds(eta, m1, m2, n_iter=args.lanczos, tol=1e-8, **solver)
+    tmin, tmax, rmin, rmax, stb = ctx.meofa_bounds(eta, m1, m2, n_iter=args.lanczos, tol=args.lanczos_tol, **solver)
     t_bounds = time.perf_counter() - t0
     log(f"heatbath: Lanczos ({args.lanczos} steps, {t_bounds:.1f} s): theta [{tmin:.6f}, {tmax:.6f}], "
         f"residuals {rmin:.2e}, {rmax:.2e}")
@@ -330,7 +330,7 @@ def hmc(args):
     sync = torch.cuda.synchronize
     sync()
     t0 = time.perf_counter()
-    tmin, tmax, rmin, rmax, _ = ctx.meofa_bounds(eta, m1, m2, n_iter=args.lanczos, tol=1e-8, inner=args.inner)
+    tmin, tmax, rmin, rmax, _ = ctx.meofa_bounds(eta, m1, m2, n_iter=args.lanczos, tol=args.lanczos_tol, inner=args.inner)
     lo, hi = 0.98 * max(tmin - rmin, 0.5 * tmin), 1.02 * (tmax + rmax)
     n_poles = next(k for k in range(1, 65) if rational_inv_sqrt(lo, hi, k)[3] <= 1e-10)
     sync()
@@ -346,6 +346,7 @@ def hmc(args):
     t_h0 = time.perf_counter() - t0
     prog = lambda i, st: log(f"hmc: force {i}: iters {st['iters']} solve {st['seconds']:.2f}s")
     t0 = time.perf_counter()
+    ctx.chrono(args.chrono)
     fst = force_gradient(ctx, U, P, phi, m1, m2, n, dt, progress=prog, **solver)
     sync()
     t_md = time.perf_counter() - t0
@@ -370,7 +371,7 @@ def hmc(args):
                       "force_gradient_integration": t_md / total, "energies": (t_h0 + t_h1) / total},
            "heatbath": {"n_poles": n_poles, "interval": [lo, hi], "iters": hb["iters"],
                         "S0_over_eta2_minus_1": S0 / ee - 1.0},
-           "md": {"force_evaluations": len(fst), "solve_iters_total": [sum(s["iters"][0] for s in fst),
+           "md": {"force_evaluations": len(fst), "chrono": args.chrono, "solve_iters_total": [sum(s["iters"][0] for s in fst),
                                                                         sum(s["iters"][1] for s in fst)]},
            "dH": dH, "H0": H0, "accept_probability": float(min(1.0, np.exp(-dH)))}
     print(json.dumps(out), flush=True)
@@ -395,12 +396,16 @@ def main():
                     help="instead of the step benchmark: the EOFA heatbath of eq. (3.1) (Lanczos interval, "
                          "Zolotarev poles, 2 N_p solves) on the selected workload")
     ap.add_argument("--lanczos", type=int, default=16, help="Lanczos steps for the heatbath interval")
+    ap.add_argument("--lanczos-tol", type=float, default=1e-6,
+                    help="solver tolerance inside the Lanczos steps (the interval needs ~1 %% accuracy)")
     ap.add_argument("--forecast", type=int, default=8,
                     help="heatbath: earlier solutions per side for chronological initial guesses (0: none)")
     ap.add_argument("--hmc", action="store_true",
                     help="instead of the step benchmark: one full EOFA HMC trajectory (heatbath, force-gradient "
                          "integration, energies) on the 24^3x64 trajectory workload, timed by phase")
     ap.add_argument("--md-steps", type=int, default=12, help="hmc: force-gradient steps per unit trajectory")
+    ap.add_argument("--chrono", type=int, default=8,
+                    help="hmc: earlier solutions per system for chronological guesses in the MD (0: none)")
     ap.add_argument("--dslash", action="store_true",
                     help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
     ap.add_argument("--copy-calibration", action="store_true",

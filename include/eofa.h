@@ -176,6 +176,19 @@ int eofa_meofa_bounds(eofa_ctx_t *ctx, double m1, double m2, const void *start_d
                       const eofa_solver_t *solver, double *theta_out, double *resid_out,
                       eofa_stats_t *stats);
 
+/* Chronological initial guesses across solves (the technique of Section 5.2,
+ * Brower et al., applied to the molecular dynamics).  With depth > 0, every
+ * solve of eofa_solve and eofa_force without an explicit initial guess
+ * starts each EOFA system from the combination of that system's last
+ * `depth` solutions (at the same masses) that minimises its residual with
+ * the current links, and then adds its own solution to the history.
+ * depth = 0 turns this off.  Every call clears the history: call it when the
+ * pseudofermion changes (each trajectory).  0 <= depth <= 16; the context
+ * then holds 3 * depth extra FP64 half fields.  With a history the
+ * solutions depend on earlier calls, so molecular-dynamics reversibility
+ * holds to the solver tolerance rather than to rounding. */
+int eofa_chrono(eofa_ctx_t *ctx, int depth);
+
 /* Pseudofermion force of eq. (3.2):
  *   d^a_{x,mu} S = k chi_L^dag g5 R5 (d^a D_w) chi_L - k chi_R^dag g5 R5 (d^a D_w) chi_R,
  * d^a the derivative along U_mu(x) -> exp(i eps T^a) U_mu(x), T^a = lambda^a/2.

@@ -16,7 +16,7 @@ PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 
 EXPORTS = [
     "eofa_ctx_create", "eofa_ctx_destroy", "eofa_ctx_update_gauge", "dwf_apply", "eofa_solve",
-    "eofa_force", "eofa_md_update", "eofa_rational_inv_sqrt", "eofa_heatbath", "eofa_meofa_bounds",
+    "eofa_force", "eofa_md_update", "eofa_rational_inv_sqrt", "eofa_heatbath", "eofa_meofa_bounds", "eofa_chrono",
     "eofa_timing_enable",
     "eofa_timing_query", "eofa_last_error",
 ]
@@ -71,6 +71,7 @@ def load() -> C.CDLL:
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "eofa_heatbath": (I_, [P, D, D, P, I_, D, C.POINTER(C.c_double), C.POINTER(C.c_double), I_, P,
                                C.POINTER(Solver), C.POINTER(Stats)]),
+        "eofa_chrono": (I_, [P, I_]),
         "eofa_meofa_bounds": (I_, [P, D, D, P, I_, C.POINTER(Solver), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(Stats)]),
         "eofa_timing_enable": (I_, [P, I_]),

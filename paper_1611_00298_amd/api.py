@@ -163,6 +163,12 @@ class Context:
         d["delta"] = delta
         return phi, d
 
+    # -- eofa_chrono ------------------------------------------------------------
+    def chrono(self, depth):
+        """Chronological initial guesses across solves from the last `depth`
+        solutions per system (0: off); clears the history."""
+        check(self.lib.eofa_chrono(self.handle, int(depth)))
+
     # -- eofa_meofa_bounds -----------------------------------------------------
     def meofa_bounds(self, start, m1, m2, n_iter=20, tol=1e-8, maxiter=20000, inner="fp16",
                      reliable_delta=0.3, allow_noconv=False):

@@ -143,6 +143,11 @@ struct eofa_ctx {
     hipEvent_t ring_ev[2] = {nullptr, nullptr};
     std::map<std::string, Half> ws;
     std::map<std::string, void*> raw;
+    // chronological guesses across solves (eofa_chrono): depth, solutions
+    // stored per system (L, R) and the masses they were taken at
+    int chrono_k = 0;
+    int chrono_n[2] = {0, 0};
+    double chrono_m[2][2] = {{0, 0}, {0, 0}};
     // timing
     bool timing = false;
     std::vector<hipEvent_t> evpool;
@@ -841,8 +846,26 @@ int solve_impl(eofa_ctx* c, double m1, double m2, const void* phi, const void* x
             local_op(c, P64, ce, ye, I5, DtInv(c, 0), mp, mm);
             local_op(c, P64, co, yo, I5, DtInv(c, 0), mp, mm);
         }
+        // chronological guess from this system's earlier solutions (same masses)
+        const int K = x0 ? 0 : c->chrono_k;
+        std::vector<Half*> hist, wv;
+        int& cnt = c->chrono_n[sys];
+        if (K > 0) {
+            if (c->chrono_m[sys][0] != mp || c->chrono_m[sys][1] != mm) cnt = 0;
+            for (int i = 0; i < K; ++i) {
+                hist.push_back(&ws(c, std::string(sys ? "ch_R" : "ch_L") + std::to_string(i), P64));
+                wv.push_back(&ws(c, "fc_W" + std::to_string(i), P64));
+            }
+        }
+        const Forecast fc{hist.data(), wv.data(), std::min(cnt, K)};
         CayleyOut o = solve_cayley(c, mp, mm, sys ? bRe : bLe, sys ? bRo : bLo, ye, yo, x0 != nullptr,
-                                   ce, co, *sp);
+                                   ce, co, *sp, K > 0 && cnt > 0 ? &fc : nullptr);
+        if (K > 0) {
+            convert(c, yo, *hist[cnt % K]);
+            ++cnt;
+            c->chrono_m[sys][0] = mp;
+            c->chrono_m[sys][1] = mm;
+        }
         hipchk(launch_dev_to_nat5(sys ? chiR : chiL, ce.d, co.d, c->L, c->Ls, c->N, c->st), "layout");
         if (stats) {
             stats->iters[sys] = o.iters;
@@ -1405,6 +1428,16 @@ int eofa_solve(eofa_ctx_t* c, double m1, double m2, const void* phi, const void*
                void* chiL, void* chiR, void* Mphi, double* S, const eofa_solver_t* sp,
                eofa_stats_t* stats) {
     return guarded([&]() -> int { return solve_impl(c, m1, m2, phi, x0L, x0R, chiL, chiR, Mphi, S, sp, stats); });
+}
+
+int eofa_chrono(eofa_ctx_t* c, int depth) {
+    return guarded([&] {
+        if (!c) fail(EOFA_EINVAL, "NULL argument");
+        if (depth < 0 || depth > 16) fail(EOFA_EINVAL, "depth must be in [0, 16]");
+        c->chrono_k = depth;
+        c->chrono_n[0] = c->chrono_n[1] = 0;
+        return EOFA_OK;
+    });
 }
 
 int eofa_rational_inv_sqrt(double lo, double hi, int n, double* alpha0, double* alpha, double* beta,

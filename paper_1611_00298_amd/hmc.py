@@ -93,16 +93,19 @@ def force_gradient(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, 
 
 
 def trajectory(ctx: Context, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_accept=None,
-               integrator=None, progress=None, **solver):
+               integrator=None, progress=None, chrono=0, **solver):
     """One HMC trajectory from links U and fresh momenta P (both updated in
     place; restored on rejection):
     phi = M_EOFA^(-1/2) eta (eq. (3.1), Zolotarev on [lo, hi] with n_poles),
     H0 = sum tr P^2 + S(phi), the molecular dynamics (`integrator`: leapfrog
     (default) or force_gradient), H1, then accept if u_accept < exp(-(H1 - H0)) (always accept
-    when u_accept is None).  Returns a dict with H0, dH, accepted and the
-    heatbath and force statistics."""
+    when u_accept is None).  chrono > 0 starts the molecular-dynamics solves
+    from chronological guesses over the last `chrono` solutions (history
+    cleared here, since phi is new).  Returns a dict with H0, dH, accepted
+    and the heatbath and force statistics."""
     ctx.update_gauge(U)
     phi, hb = ctx.eofa_heatbath(eta, m1, m2, lo=lo, hi=hi, n_poles=n_poles, **solver)
+    ctx.chrono(chrono)
     U0, P0 = U.clone(), P.clone()
     H0, S0, _, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
     step = integrator or leapfrog

@@ -68,6 +68,7 @@ def test_null_arguments_are_rejected():
                              None) == _lib.EOFA_EINVAL
     assert lib.eofa_meofa_bounds(None, 0.1, 0.2, None, 10, C.byref(sp), None, None,
                                  None) == _lib.EOFA_EINVAL
+    assert lib.eofa_chrono(None, 4) == _lib.EOFA_EINVAL
     lib.eofa_ctx_destroy(None)
 
 
