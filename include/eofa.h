@@ -118,7 +118,7 @@ int eofa_solve(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
                const void *x0_L_dev, const void *x0_R_dev, void *chiL_dev, void *chiR_dev,
                void *Mphi_dev, double *S_out, const eofa_solver_t *solver, eofa_stats_t *stats);
 
-/* Rational approximation for the heatbath of Section 3.1: the best
+/* Rational approximation for the heatbath of Section 3.2: the best
  * relative-error approximation of x^(-1/2) on [lo, hi] of type (n, n),
  *   x^(-1/2) ~ alpha0 + sum_{l<n} alpha[l] / (beta[l] + x),
  * from Zolotarev's closed form (Jacobi elliptic functions by the
@@ -161,7 +161,7 @@ int eofa_heatbath(eofa_ctx_t *ctx, double m1, double m2, const void *eta_dev, in
                   void *phi_dev, const eofa_solver_t *solver, eofa_stats_t *stats);
 
 /* Extreme eigenvalues of M_EOFA (eq. (2.5)), for choosing the interval of
- * the rational heatbath (Section 3.1): n_iter Lanczos steps from start_dev
+ * the rational heatbath (Section 3.2): n_iter Lanczos steps from start_dev
  * (4D device field, natural layout; any nonzero vector), each applying
  * M_EOFA once, i.e. two Cayley-form solves with `solver` as in eofa_solve.
  *   theta_out[2]: the smallest and largest Ritz values;

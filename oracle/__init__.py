@@ -315,7 +315,7 @@ def kinetic(P) -> float:
 
 
 # ---------------------------------------------------------------------------
-# heatbath (Section 3.1, eq. (3.1)) -- plain numpy on top of H_op
+# heatbath (Section 3.2, eq. (3.1)) -- plain numpy on top of H_op
 # ---------------------------------------------------------------------------
 
 def zolotarev_inv_sqrt(lo: float, hi: float, n: int):

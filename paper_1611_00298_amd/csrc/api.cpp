@@ -1056,7 +1056,7 @@ void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& Z) {
 // Lanczos on M_EOFA (Hermitian positive definite, Section 2) from `start`:
 // the extreme Ritz values of the tridiagonal T_j and their residual norms
 // beta_j |s_j| (s_j the last component of the Ritz vector), for choosing the
-// interval of the rational heatbath of Section 3.1.
+// interval of the rational heatbath of Section 3.2.
 int bounds_impl(eofa_ctx* c, double m1, double m2, const void* start, int n_iter, const eofa_solver_t* sp,
                 double* theta, double* resid, eofa_stats_t* stats) {
     if (!c || !start || !theta) fail(EOFA_EINVAL, "NULL argument");

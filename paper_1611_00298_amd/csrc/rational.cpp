@@ -1,4 +1,4 @@
-// Rational approximation of x^(-1/2) for the EOFA heatbath (Section 3.1).
+// Rational approximation of x^(-1/2) for the EOFA heatbath (Section 3.2).
 //
 // The heatbath needs x^(-1/2) ~ alpha0 + sum_l alpha_l / (beta_l + x) on an
 // interval [lo, hi] that holds the spectrum of M_EOFA.  The best such

@@ -45,7 +45,7 @@ def leapfrog(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, **solv
     return stats
 
 
-# Force-gradient QPQPQ step (the integrator family of Section 4):
+# Force-gradient QPQPQ step (the integrator family of Section 5):
 #   U <- e^{i lam h P} U;  P <- P - (h/2) F~;  U <- e^{i (1 - 2 lam) h P} U;
 #   P <- P - (h/2) F~;  U <- e^{i lam h P} U,
 # with F~ = F(U') at links moved along the force, U' = exp(-i xi h^2 F(U)) U.

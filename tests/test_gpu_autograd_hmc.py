@@ -100,7 +100,7 @@ def test_mixed_precision_trajectory_against_fp64(c1):
 
 
 def test_force_gradient_dt4_scaling_and_reversibility(c1):
-    """The force-gradient QPQPQ integrator (Section 4's integrator family):
+    """The force-gradient QPQPQ integrator (Section 5's integrator family):
     the energy violation falls like dt^4, it beats leapfrog at the same step,
     and it is reversible."""
     from paper_1611_00298_amd.hmc import force_gradient, hamiltonian

@@ -63,7 +63,7 @@ def test_heatbath_interval_form_c1(c1_heatbath):
 def test_heatbath_is_inverse_square_root_dense(inner):
     """On 2x2x2x4, Ls = 4, M_EOFA is built densely by the oracle: the GPU phi
     equals M^(-1/2) eta to within the approximation error delta on an
-    interval holding the spectrum (Section 3.1)."""
+    interval holding the spectrum (Section 3.2)."""
     from paper_1611_00298_amd import Context
     lat = oracle.Lattice((2, 2, 2, 4), 4, M5=1.8, alpha=2.0)
     U = din.random_gauge(lat.L, 0.3, 11)

@@ -517,7 +517,7 @@ def test_md_exponential():
 
 
 # --------------------------------------------------------------------------
-# heatbath (Section 3.1, eq. (3.1))
+# heatbath (Section 3.2, eq. (3.1))
 # --------------------------------------------------------------------------
 
 def alternation_runs(e, level):
@@ -603,7 +603,7 @@ def test_heatbath_is_the_rational_function_of_M(dense_heatbath):
 def test_heatbath_draws_from_M_eofa(dense_heatbath):
     """phi = M^(-1/2) eta to within the approximation's error: with the
     spectrum inside [lo, hi], |phi - M^(-1/2) eta| <= delta |M^(-1/2) eta|,
-    and phi^dag M phi = eta^dag eta (1 + O(delta)) (Section 3.1)."""
+    and phi^dag M phi = eta^dag eta (1 + O(delta)) (Section 3.2)."""
     lat, U, m1, m2, M, lam, V, eta = dense_heatbath
     assert lam[0] > 0 and lam[-1] / lam[0] > 1.05    # a non-trivial spectrum
     n = M.shape[0]
