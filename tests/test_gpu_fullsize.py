@@ -148,3 +148,21 @@ def test_c2_force_sampled(c2):
     Gg = G.view(4, lat.V, 3, 3)[links[:, 0], links[:, 1]].cpu().numpy()
     assert np.abs(Fg - Fr).max() <= 1e-12 * np.abs(Fr).max()
     assert np.abs(Gg - Gr).max() <= 1e-12 * np.abs(Gr).max()
+
+
+def test_c3_heatbath_property(c3):
+    """The heatbath of eq. (3.1) at 24^3x64, Ls = 24, as bench.py runs it
+    (FP16 inner, chronological guesses across poles): phi^dag M_EOFA phi
+    equals eta^dag eta up to the approximation error, with S from a fresh
+    GPU solve.  [0.5, 40] holds M_EOFA's spectrum here ([1.007, 26.97] by
+    Lanczos) with a wide margin."""
+    from paper_1611_00298_amd import rational_inv_sqrt
+    pre, lat, U, psi, ctx = c3
+    eta = din.gaussian_4d(pre["L"], pre["seed_phi"])
+    n = next(k for k in range(1, 40) if rational_inv_sqrt(0.5, 40.0, k)[3] <= 1e-10)
+    phi, st = ctx.eofa_heatbath(to_dev(eta), pre["m1"], pre["m2"], lo=0.5, hi=40.0, n_poles=n, tol=1e-10,
+                                inner="fp16")
+    assert st["converged"] and max(st["true_resid"]) <= 1e-10
+    _, _, _, S, _ = ctx.eofa_solve(phi, pre["m1"], pre["m2"], tol=1e-10, inner="fp16", want_mphi=False)
+    ee = float(np.vdot(eta, eta).real)
+    assert abs(S / ee - 1.0) <= 2 * st["delta"] + 1e-9, (S / ee - 1.0, st["delta"])
