@@ -173,6 +173,13 @@ def test_chronological_guesses(c1):
     assert max(st2["iters"]) <= 0.2 * min(st1["iters"]), (st1["iters"], st2["iters"])
     assert max(st2["true_resid"]) <= 1e-11
     assert S2 == pytest.approx(S, rel=1e-10)
+    # other masses: that history is not used; the solve is as from zero and correct
+    ctx.chrono(0)
+    _, _, _, S3, st3 = ctx.eofa_solve(ph, 0.1, 0.5, tol=1e-11)
+    ctx.chrono(4)
+    ctx.eofa_solve(ph, C1["m1"], C1["m2"], tol=1e-11)
+    _, _, _, S4, st4 = ctx.eofa_solve(ph, 0.1, 0.5, tol=1e-11)
+    assert st4["iters"] == st3["iters"] and S4 == pytest.approx(S3, rel=1e-10)
     P0 = din.gaussian_momenta(C1["L"], 309)
     res = {}
     for depth in (0, 6):
