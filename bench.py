@@ -282,6 +282,10 @@ def heatbath(args):
     _, _, _, S, stc = ctx.eofa_solve(phi, m1, m2, tol=1e-10, want_mphi=False, **solver)
     ee = float(np.vdot(eta_h, eta_h).real)
     ctx.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = heatbath_cpu_baseline(solver)
+        log(f"heatbath: oracle on {cpu['sample']}: {cpu['value']:.1f} s, GPU on the same: {cpu['gpu_seconds']:.2f} s")
     out = {"metric": "EOFA heatbath (eq. 3.1): time for phi = M_EOFA^-1/2 eta (1 GPU)",
            "value": t_hb, "unit": "s", "higher_is_better": False,
            "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
@@ -295,11 +299,46 @@ def heatbath(args):
                         "reliable_updates": st["reliable_updates"], "true_resid": st["true_resid"]},
            "hop": {"launches": hq["count"], "avg_ms": hq["ms"] / max(hq["count"], 1),
                    "achieved_GBs": hq["bytes"] / max(hq["ms"], 1e-30) / 1e6,
+                   "peak_GBs": HBM_PEAK_GBS, "frac": hq["bytes"] / max(hq["ms"], 1e-30) / 1e6 / HBM_PEAK_GBS,
                    "time_share": hq["ms"] / 1e3 / t_hb},
+           "cpu_baseline": cpu,
            "check": {"S_over_eta2_minus_1": S / ee - 1.0, "bound_2delta": 2 * st["delta"],
                      "solve_iters": stc["iters"]}}
     print(json.dumps(out), flush=True)
     return 0
+
+
+def heatbath_cpu_baseline(solver):
+    """The oracle's heatbath (eq. (3.1) as printed: CGNR on the shifted
+    operators, FP64, OpenMP) on the 4^4x8, Ls = 8 case with 4 Zolotarev
+    poles on [0.5, 3], beside the GPU heatbath on the same input."""
+    import torch
+    import dwf_inputs as din
+    import oracle
+    from paper_1611_00298_amd import Context
+    pre = din.preset("c1")
+    lat = oracle.Lattice(pre["L"], pre["Ls"], M5=pre["M5"], alpha=pre["alpha"])
+    U = din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"])
+    eta = din.gaussian_4d(pre["L"], pre["seed_phi"])
+    a0, a, b, _ = oracle.zolotarev_inv_sqrt(0.5, 3.0, 4)
+    t0 = time.perf_counter()
+    ref, _ = oracle.eofa_heatbath(lat, U, pre["m1"], pre["m2"], eta, a0, a, b, tol=1e-10)
+    t_cpu = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    with Context(pre["L"], pre["Ls"], torch.from_numpy(U).to(dev), M5=pre["M5"], alpha=pre["alpha"]) as ctx:
+        e = torch.from_numpy(eta).to(dev)
+        ctx.eofa_heatbath(e, pre["m1"], pre["m2"], coeffs=(a0, a, b), tol=1e-10, **solver)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, _ = ctx.eofa_heatbath(e, pre["m1"], pre["m2"], coeffs=(a0, a, b), tol=1e-10, **solver)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t0
+    import numpy as np
+    diff = float(np.linalg.norm(phi.cpu().numpy() - ref) / np.linalg.norm(ref))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": t_cpu, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": "eq. (3.1) heatbath on 4^4x8, Ls=8, 4 poles on [0.5, 3], solves to 1e-10",
+            "gpu_seconds": t_gpu, "rel_diff_gpu_vs_oracle": diff}
 
 
 def hmc(args):
