@@ -1144,22 +1144,22 @@ int guarded(F&& f) {
 
 void free_ctx(eofa_ctx* c) {
     if (!c) return;
-    if (c->st) hipStreamSynchronize(c->st);
-    for (auto& kv : c->ws) { hipFree(kv.second.d); if (kv.second.nrm) hipFree(kv.second.nrm); }
-    for (auto& kv : c->raw) hipFree(kv.second);
-    for (int p = 0; p < 4; ++p) if (c->gauge[p]) hipFree(c->gauge[p]);
-    for (int p = 0; p < 4; ++p) if (c->sites[p]) hipFree(c->sites[p]);
-    if (c->nbr) hipFree(c->nbr);
-    if (c->U_nat) hipFree(c->U_nat);
-    if (c->frag) hipFree(c->frag);
-    if (c->frag_b) hipFree(c->frag_b);
-    if (c->om) hipFree(c->om);
-    if (c->partial) hipFree(c->partial);
-    if (c->sc) hipFree(c->sc);
-    if (c->pinned) hipHostFree(c->pinned);
-    if (c->ring) hipHostFree(c->ring);
-    for (auto e : c->ring_ev) if (e) hipEventDestroy(e);
-    for (auto e : c->evpool) hipEventDestroy(e);
+    if (c->st) (void)hipStreamSynchronize(c->st);   // teardown: errors cannot be reported
+    for (auto& kv : c->ws) { (void)hipFree(kv.second.d); if (kv.second.nrm) (void)hipFree(kv.second.nrm); }
+    for (auto& kv : c->raw) (void)hipFree(kv.second);
+    for (int p = 0; p < 4; ++p) if (c->gauge[p]) (void)hipFree(c->gauge[p]);
+    for (int p = 0; p < 4; ++p) if (c->sites[p]) (void)hipFree(c->sites[p]);
+    if (c->nbr) (void)hipFree(c->nbr);
+    if (c->U_nat) (void)hipFree(c->U_nat);
+    if (c->frag) (void)hipFree(c->frag);
+    if (c->frag_b) (void)hipFree(c->frag_b);
+    if (c->om) (void)hipFree(c->om);
+    if (c->partial) (void)hipFree(c->partial);
+    if (c->sc) (void)hipFree(c->sc);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->ring) (void)hipHostFree(c->ring);
+    for (auto e : c->ring_ev) if (e) (void)hipEventDestroy(e);
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
     delete c;
 }
 
