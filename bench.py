@@ -434,8 +434,8 @@ def main():
     ap.add_argument("--heatbath", action="store_true",
                     help="instead of the step benchmark: the EOFA heatbath of eq. (3.1) (Lanczos interval, "
                          "Zolotarev poles, 2 N_p solves) on the selected workload")
-    ap.add_argument("--lanczos", type=int, default=16, help="Lanczos steps for the heatbath interval")
-    ap.add_argument("--lanczos-tol", type=float, default=1e-6,
+    ap.add_argument("--lanczos", type=int, default=12, help="Lanczos steps for the heatbath interval")
+    ap.add_argument("--lanczos-tol", type=float, default=1e-5,
                     help="solver tolerance inside the Lanczos steps (the interval needs ~1 %% accuracy)")
     ap.add_argument("--forecast", type=int, default=8,
                     help="heatbath: earlier solutions per side for chronological initial guesses (0: none)")
