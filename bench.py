@@ -18,6 +18,12 @@ per inverse 5D op), the roofline of the dominant kernel (the 5D hopping
 kernel, measured with HIP events inside the timed region), the FP64-solver
 reference time on the same GPU, and the CPU oracle's operator rate on a
 bounded sample.
+
+Other modes, each printing its own JSON line instead:
+  --dslash      the hopping kernel's rate in all four precisions
+  --trajectory  the 24^3x64 leapfrog trajectory, mixed vs FP64 (dH, reversibility)
+  --heatbath    the eq. (3.1) heatbath: Lanczos interval, Zolotarev poles, 2 N_p solves
+  --hmc         one full trajectory (heatbath, force-gradient MD, energies) by phase
 """
 from __future__ import annotations
 
