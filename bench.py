@@ -457,8 +457,8 @@ def main():
                     help="run 3 x 2 GiB device copies first (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "a design (4D domain decomposition), not implemented"}))
+        print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding "
+                                   "(4D domain decomposition) is not implemented"}))
         return 2
 
     if args.trajectory:
