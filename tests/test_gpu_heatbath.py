@@ -147,6 +147,22 @@ def test_heatbath_errors(c1_heatbath):
         assert e.value.code == _lib.EOFA_EINVAL
         with pytest.raises(ValueError):
             ctx.eofa_heatbath(eta_d, 0.04, 1.0)
+        # a solve that cannot finish: ENOCONV, phi still written, statistics filled
+        with pytest.raises(_lib.EOFAError) as e:
+            ctx.eofa_heatbath(eta_d, C1["m1"], C1["m2"], coeffs=(a0, a, b), maxiter=3)
+        assert e.value.code == _lib.EOFA_ENOCONV
+        phi, st = ctx.eofa_heatbath(eta_d, C1["m1"], C1["m2"], coeffs=(a0, a, b), maxiter=3,
+                                    allow_noconv=True)
+        assert not st["converged"] and st["iters"][0] > 0 and np.isfinite(phi.cpu().numpy()).all()
+        # Lanczos steps and history depth out of range
+        for n_iter in (1, 201):
+            with pytest.raises(_lib.EOFAError) as e:
+                ctx.meofa_bounds(eta_d, C1["m1"], C1["m2"], n_iter=n_iter)
+            assert e.value.code == _lib.EOFA_EINVAL
+        for depth in (-1, 17):
+            with pytest.raises(_lib.EOFAError) as e:
+                ctx.chrono(depth)
+            assert e.value.code == _lib.EOFA_EINVAL
 
 
 def test_meofa_bounds_dense():
