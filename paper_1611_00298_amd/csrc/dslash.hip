@@ -545,48 +545,67 @@ __device__ __forceinline__ A ipow(A x, int e) {
     return r;
 }
 
-// in-place column ops; element at position q along the shift is col[sq(q)*STR]
-template <typename A>
-__device__ void col_bidiag(A* col, int Ls, bool down, A a, A b, A m) {
-    const int s0 = down ? 0 : Ls - 1, ds = down ? 1 : -1;
-    A prev = -m * col[(s0 + ds * (Ls - 1)) * STR];
-    int sidx = s0;
-    for (int q = 0; q < Ls; ++q, sidx += ds) {
-        const A x = col[sidx * STR];
-        col[sidx * STR] = fmadd(b, prev, a * x);
-        prev = x;
+// One in-order pass over a column: x_q <- f(x_q) for q = 0 .. Ls-1 at
+// col[(s0 + ds q) STR], with f a (stateful) recursion step.  Loads are
+// issued in batches of CB before the batch's stores, so a pass waits for the
+// LDS latency once per batch rather than once per element (CB is set per
+// precision by the registers it can spare).
+template <int CB, typename A, typename F>
+__device__ __forceinline__ void col_pass(A* col, int Ls, int s0, int ds, F&& f) {
+    int q = 0;
+    for (; q + CB <= Ls; q += CB) {
+        A x[CB];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) x[i] = col[(s0 + ds * (q + i)) * STR];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) col[(s0 + ds * (q + i)) * STR] = f(x[i]);
+    }
+    for (; q < Ls; ++q) {
+        const int id = (s0 + ds * q) * STR;
+        col[id] = f(col[id]);
     }
 }
 
-template <typename A>
+// in-place column ops; element at position q along the shift is col[sq(q)*STR]
+template <int CB, typename A>
+__device__ void col_bidiag(A* col, int Ls, bool down, A a, A b, A m) {
+    const int s0 = down ? 0 : Ls - 1, ds = down ? 1 : -1;
+    A prev = -m * col[(s0 + ds * (Ls - 1)) * STR];
+    col_pass<CB>(col, Ls, s0, ds, [&](A x) {
+        const A y = fmadd(b, prev, a * x);
+        prev = x;
+        return y;
+    });
+}
+
+template <int CB, typename A>
 __device__ void col_inverse(A* col, int Ls, bool down, A a, A b, A m) {
     const int s0 = down ? 0 : Ls - 1, ds = down ? 1 : -1;
     const A ia = A(1) / a, w = -b * ia;
     A z = 0;
-    int sidx = s0;
-    for (int q = 0; q < Ls; ++q, sidx += ds) {
-        z = fmadd(w, z, ia * col[sidx * STR]);
-        col[sidx * STR] = z;
-    }
+    col_pass<CB>(col, Ls, s0, ds, [&](A x) {
+        z = fmadd(w, z, ia * x);
+        return z;
+    });
     const A K = -m * z / (A(1) + m * ipow(w, Ls));
     A pw = w;
-    sidx = s0;
-    for (int q = 0; q < Ls; ++q, sidx += ds) {
-        col[sidx * STR] = fmadd(K, pw, col[sidx * STR]);
+    col_pass<CB>(col, Ls, s0, ds, [&](A x) {
+        const A y = fmadd(K, pw, x);
         pw *= w;
-    }
+        return y;
+    });
 }
 
-template <typename A>
+template <int CB, typename A>
 __device__ __forceinline__ void col_op(A* col, int Ls, bool upper, const Op5& op, A mp, A mm) {
     const bool down = upper != (op.tr != 0);
     const A m = upper ? mp : mm;
-    if (op.kind == 1) col_bidiag(col, Ls, down, (A)op.a, (A)op.b, m);
-    else if (op.kind == 2) col_inverse(col, Ls, down, (A)op.a, (A)op.b, m);
+    if (op.kind == 1) col_bidiag<CB>(col, Ls, down, (A)op.a, (A)op.b, m);
+    else if (op.kind == 2) col_inverse<CB>(col, Ls, down, (A)op.a, (A)op.b, m);
 }
 
 // v <- op2(scale * op1(v)) through a column sweep of the staged tile
-template <typename A>
+template <int CB, typename A>
 __device__ void column_phase(A* T, int tid, int sl, int s, int Ls, A (&v)[24], const Op5& op1,
                              A scale, const Op5& op2, A mp, A mm) {
     put_row(T, tid, v);
@@ -594,10 +613,9 @@ __device__ void column_phase(A* T, int tid, int sl, int s, int Ls, A (&v)[24], c
     for (int c = s; c < 24; c += Ls) {
         A* col = T + sl * Ls * STR + c;
         const bool upper = c < 12;
-        col_op(col, Ls, upper, op1, mp, mm);
-        if (scale != A(1))
-            for (int q = 0; q < Ls; ++q) col[q * STR] *= scale;
-        col_op(col, Ls, upper, op2, mp, mm);
+        col_op<CB>(col, Ls, upper, op1, mp, mm);
+        if (scale != A(1)) col_pass<CB>(col, Ls, 0, 1, [&](A x) { return x * scale; });
+        col_op<CB>(col, Ls, upper, op2, mp, mm);
     }
     __syncthreads();
     get_row(T, tid, v);
@@ -620,8 +638,10 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 }
 
 template <int P, bool DAG, bool HOP, int MF>
-__global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
+__global__ void __launch_bounds__(256, (MF == 3 && P == P16) ? 5 : 3) k_hop(const HopArgs a) {
     using A = typename PT<P>::A;
+    // column-sweep load batch: what each variant's register budget allows
+    constexpr int COLB = P == P64 ? 1 : (P == P16 && MF) ? 4 : 8;
     extern __shared__ unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
     __shared__ double red[16];
@@ -678,7 +698,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
             aux2_done = true;
         }
         if (a.opA.kind != 0 || a.opC.kind != 0) {
-            column_phase(lds, tid, sl, s, Ls, v, a.opA, ch, a.opC, mp, mm);
+            column_phase<COLB>(lds, tid, sl, s, Ls, v, a.opA, ch, a.opC, mp, mm);
         } else if (ch != A(1)) {
 #pragma unroll
             for (int k = 0; k < 24; ++k) v[k] *= ch;
@@ -692,7 +712,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
             }
             const A ca = (A)(a.ca * alpha);
             if (a.opB2.kind != 0) {
-                column_phase(lds, tid, sl, s, Ls, x, a.opB, ca, a.opB2, mp, mm);
+                column_phase<COLB>(lds, tid, sl, s, Ls, x, a.opB, ca, a.opB2, mp, mm);
 #pragma unroll
                 for (int k = 0; k < 24; ++k) v[k] += x[k];
             } else if (a.opB.kind == 1) {
@@ -719,7 +739,7 @@ __global__ void __launch_bounds__(256, 3) k_hop(const HopArgs a) {
         // local 5D operator: out = C(ca * B(aux)) + cr * aux2
         if (active) ld_spinor<P>(a.aux, a.aux_nrm, a.N, n, v);
         if (a.opB.kind != 0 || a.opC.kind != 0) {
-            column_phase(lds, tid, sl, s, Ls, v, a.opB, (A)(a.ca * alpha), a.opC, mp, mm);
+            column_phase<COLB>(lds, tid, sl, s, Ls, v, a.opB, (A)(a.ca * alpha), a.opC, mp, mm);
         } else {
             const A ca = (A)(a.ca * alpha);
 #pragma unroll
