@@ -497,6 +497,8 @@ def main():
         P.copy_(P0)
         ctx.update_gauge(U)
 
+    last = {}
+
     def step(record):
         restart()
         chiL, chiR, _, S, st = ctx.eofa_solve(phi, m1, m2, want_mphi=False, **solver)
@@ -505,6 +507,7 @@ def main():
         ctx.update_gauge(U)
         if record is not None:
             record.append(dict(S=S, kin=kin, **st))
+            last["chi"] = (chiL, chiR)   # compared with the FP64 solve after the timed region
         return st
 
     for w in range(args.warmup):
@@ -580,12 +583,18 @@ def main():
         restart()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        _, _, _, S64, st64 = ctx.eofa_solve(phi, m1, m2, want_mphi=False, tol=tol, inner="fp64")
+        chiL64, chiR64, _, S64, st64 = ctx.eofa_solve(phi, m1, m2, want_mphi=False, tol=tol, inner="fp64")
         torch.cuda.synchronize()
         out["solve"]["fp64_s"] = time.perf_counter() - t2
         out["solve"]["fp64_iters"] = st64["iters"]
         out["solve"]["fp64_true_resid"] = st64["true_resid"]
         out["solve"]["speedup_mixed_vs_fp64"] = out["solve"]["fp64_s"] / out["solve"]["mixed_s"]
+        # the mixed-precision solution against the FP64 one (same systems, both to the true-residual target)
+        rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        cl, cr = last["chi"]
+        out["solve"]["mixed_vs_fp64"] = {"chi_L_rel": rel(cl, chiL64), "chi_R_rel": rel(cr, chiR64),
+                                         "S_rel": abs(recs[-1]["S"] - S64) / abs(S64)}
+        del chiL64, chiR64
     ctx.close()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
