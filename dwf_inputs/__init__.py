@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "PRESETS", "preset", "rng", "random_gauge", "random_su3", "gaussian_4d",
-    "gaussian_5d", "gaussian_momenta", "gell_mann", "plaquette",
+    "gaussian_5d", "gaussian_momenta", "gell_mann",
 ]
 
 # Lattice extents are given as (Lx, Ly, Lz, Lt).
@@ -132,20 +132,3 @@ def gaussian_momenta(L, seed: int) -> np.ndarray:
     p = g.standard_normal((4,) + _shape4(L) + (8,))
     T = gell_mann() / 2
     return np.einsum("...a,aij->...ij", p, T)
-
-
-def plaquette(U: np.ndarray) -> float:
-    """Average plaquette Re tr(U_mu U_nu U_mu^dag U_nu^dag)/3 (a field summary)."""
-    # axis of each direction inside U[mu] (t,z,y,x): x->3, y->2, z->1, t->0
-    ax = {0: 3, 1: 2, 2: 1, 3: 0}
-    tot, cnt = 0.0, 0
-    for mu in range(4):
-        for nu in range(mu + 1, 4):
-            Umu, Unu = U[mu], U[nu]
-            Unu_xmu = np.roll(Unu, -1, axis=ax[mu])
-            Umu_xnu = np.roll(Umu, -1, axis=ax[nu])
-            P = Umu @ Unu_xmu @ np.swapaxes(Umu_xnu.conj(), -1, -2) @ \
-                np.swapaxes(Unu.conj(), -1, -2)
-            tot += np.trace(P, axis1=-2, axis2=-1).real.sum() / 3
-            cnt += Umu.shape[0] * Umu.shape[1] * Umu.shape[2] * Umu.shape[3]
-    return tot / cnt

@@ -7,12 +7,13 @@ no code with the GPU path.
 The heavy routines live in ``oracle.c`` (plain C99, OpenMP over sites);
 this module loads them with ctypes and exposes numpy-array functions on
 fields in the natural layout (see ``dwf_inputs``).  The molecular-dynamics
-update is written here in numpy.
+update and the gauge action (loops as step lists) are written here in numpy.
 
 Parity status: every function is pinned by the CPU tests in
 ``tests/test_oracle_pins.py`` against closed forms, determinant identities,
 brute-force dense linear algebra, the free-field dispersion relation, gauge
-covariance and finite differences.
+covariance and finite differences; the gauge action by the closed form of a
+uniform abelian flux, gauge invariance and finite differences.
 """
 from __future__ import annotations
 
@@ -312,6 +313,104 @@ def md_update(U, P, F, dt_p, dt_u):
 def kinetic(P) -> float:
     """sum over links of tr(P^2) = (1/2) sum_a (p^a)^2."""
     return float((P * np.swapaxes(P, -1, -2)).sum().real)
+
+
+# ---------------------------------------------------------------------------
+# gauge action of the ensembles (Table 1: Iwasaki) -- plain numpy
+#
+# S_g = beta sum_x [ c0 sum_{mu<nu} (1 - Re tr W_plaq/3)
+#                  + c1 sum_{mu != nu} (1 - Re tr W_rect/3) ],  c0 = 1 - 8 c1,
+# W_plaq the 1x1 loop in the (mu, nu) plane and W_rect the loop two links
+# long in mu and one in nu.  c1 = -0.331 is the Iwasaki action named in
+# Table 1 (the paper gives no coefficients); c1 = 0 is the Wilson action.
+# Loops are lists of steps (+-(mu+1)); links are periodic in every direction.
+# ---------------------------------------------------------------------------
+
+IWASAKI_C1 = -0.331
+_AXIS = (3, 2, 1, 0)   # array axis of direction mu inside U[mu] (t, z, y, x)
+
+
+def _at(A, d):
+    """A(x + d) for an integer 4-vector d (periodic)."""
+    return np.roll(A, shift=tuple(-int(v) for v in d), axis=_AXIS)
+
+
+def _dag(A):
+    return np.swapaxes(A.conj(), -1, -2)
+
+
+def path_product(U, steps, start=(0, 0, 0, 0)):
+    """Field of link products along `steps` from x + start, for every x:
+    step +(mu+1) multiplies by U_mu(z) and moves z -> z + mu, step -(mu+1)
+    moves z -> z - mu and multiplies by U_mu(z)^dag."""
+    d = np.array(start, dtype=int)
+    M = None
+    for st in steps:
+        mu = abs(st) - 1
+        if st > 0:
+            f = _at(U[mu], d)
+            d[mu] += 1
+        else:
+            d[mu] -= 1
+            f = _dag(_at(U[mu], d))
+        M = f.copy() if M is None else M @ f
+    return M
+
+
+def gauge_loops(c1):
+    """(coefficient, steps) of every loop shape in S_g, each summed over x."""
+    c0 = 1.0 - 8.0 * c1
+    loops = []
+    for mu in range(4):
+        for nu in range(4):
+            a, b = mu + 1, nu + 1
+            if mu < nu:
+                loops.append((c0, [a, b, -a, -b]))
+            if mu != nu and c1 != 0.0:
+                loops.append((c1, [a, a, b, -a, -a, -b]))
+    return loops
+
+
+def gauge_action(U, beta, c1=IWASAKI_C1) -> float:
+    """S_g by summing every loop over the lattice (definition above)."""
+    S = 0.0
+    for c, steps in gauge_loops(c1):
+        W = path_product(U, steps)
+        S += c * float((1.0 - np.trace(W, axis1=-2, axis2=-1).real / 3.0).sum())
+    return beta * S
+
+
+def gauge_staples(U, c1=IWASAKI_C1):
+    """Sigma_mu(x) such that S_g depends on U_mu(x) only through
+    -(beta/3) Re tr(U_mu(x) Sigma_mu(x)) (plus terms free of U_mu(x)).
+    A loop visits U_mu(x) forwards in the rotations of the loop, or of the
+    reversed loop (Re tr W = Re tr W^dag), that start with the step +mu; the
+    staple is the rest of that rotation, walked from x + mu back to x."""
+    out = np.zeros_like(U)
+    for c, steps in gauge_loops(c1):
+        rev = [-st for st in reversed(steps)]
+        for loop in (steps, rev):
+            n = len(loop)
+            for k in range(n):
+                rot = loop[k:] + loop[:k]
+                if rot[0] < 0:
+                    continue
+                mu = rot[0] - 1
+                e = [0, 0, 0, 0]
+                e[mu] = 1
+                out[mu] += c * path_product(U, rot[1:], start=e)
+    return out
+
+
+def gauge_force(U, beta, c1=IWASAKI_C1):
+    """F_mu(x) = sum_a T^a d^a S_g, d^a along U_mu(x) -> exp(i eps T^a) U_mu(x),
+    T^a = lambda^a/2 (the convention of the fermion force).  With
+    Omega = U Sigma: d^a S_g = -(beta/3) Re tr(i T^a Omega), and by the
+    completeness of the T^a, F = -(beta/12) (Y - tr(Y)/3), Y = i (Omega - Omega^dag)."""
+    Om = U @ gauge_staples(U, c1)
+    Y = 1j * (Om - _dag(Om))
+    tr = np.trace(Y, axis1=-2, axis2=-1)[..., None, None] / 3.0
+    return -(beta / 12.0) * (Y - tr * np.eye(3))
 
 
 # ---------------------------------------------------------------------------

@@ -619,3 +619,115 @@ def test_heatbath_draws_from_M_eofa(dense_heatbath):
             assert err > 1e-3 * delta     # the bound is not vacuous here
         S = np.vdot(p, M @ p).real
         assert abs(S / np.vdot(e, e).real - 1) <= 2.01 * delta + 1e-11
+
+
+# --------------------------------------------------------------------------
+# P12: gauge action of the ensembles (Table 1: Iwasaki; c1 = 0 is Wilson)
+# --------------------------------------------------------------------------
+
+def abelian_flux_field(L, quanta):
+    """U(1) links embedded as diag(e^{i th}, e^{-i th}, 1) with a uniform flux
+    F_{mu nu} = 2 pi n_{mu nu} / (L_mu L_nu) through every plaquette of each
+    plane on the periodic lattice ('t Hooft's twisted construction):
+    th_nu(x) = sum_{mu<nu} F_{mu nu} x_mu, and on the last slice x_mu = L_mu - 1
+    th_mu also carries -sum_{nu>mu} F_{mu nu} L_mu x_nu."""
+    shape4 = (L[3], L[2], L[1], L[0])
+    t, z, y, x = np.indices(shape4)
+    X = (x, y, z, t)
+    F = {}
+    th = np.zeros((4,) + shape4)
+    for (mu, nu), n in quanta.items():
+        F[mu, nu] = 2 * np.pi * n / (L[mu] * L[nu])
+        th[nu] += F[mu, nu] * X[mu]
+        th[mu] -= np.where(X[mu] == L[mu] - 1, F[mu, nu] * L[mu] * X[nu], 0.0)
+    U = np.zeros((4,) + shape4 + (3, 3), dtype=np.complex128)
+    U[..., 0, 0] = np.exp(1j * th)
+    U[..., 1, 1] = np.exp(-1j * th)
+    U[..., 2, 2] = 1.0
+    return U, F
+
+
+def abelian_flux_action(L, F, beta, c1):
+    """Closed form of S_g for the uniform-flux field: a loop enclosing flux
+    Phi has Re tr W / 3 = (2 cos Phi + 1)/3; a plane holds one plaquette
+    (flux F) and two rectangles (flux 2F, both orientations) per site."""
+    V = L[0] * L[1] * L[2] * L[3]
+    c0 = 1 - 8 * c1
+    S = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            f = F.get((mu, nu), 0.0)
+            S += c0 * (1 - (2 * np.cos(f) + 1) / 3) + 2 * c1 * (1 - (2 * np.cos(2 * f) + 1) / 3)
+    return beta * V * S
+
+
+@pytest.mark.parametrize("c1", [0.0, oracle.IWASAKI_C1])
+def test_gauge_unit_field(c1):
+    lat = Lattice((4, 4, 4, 6), 1)
+    U = np.broadcast_to(np.eye(3, dtype=np.complex128), (4,) + lat.shape4 + (3, 3)).copy()
+    assert oracle.gauge_action(U, 2.13, c1) == 0.0
+    assert np.abs(oracle.gauge_force(U, 2.13, c1)).max() == 0.0
+
+
+@pytest.mark.parametrize("c1", [0.0, oracle.IWASAKI_C1, 0.25])
+def test_gauge_abelian_flux_closed_form(c1):
+    """Closed form of the action (each plane a different flux, so a dropped
+    plane, orientation or rectangle term shows), checked after a random gauge
+    rotation; the uniform flux is a stationary point, so the force vanishes."""
+    L = (4, 6, 4, 8)
+    quanta = {(0, 1): 1, (0, 2): 2, (0, 3): 3, (1, 2): 1, (1, 3): 5, (2, 3): 2}
+    U, F = abelian_flux_field(L, quanta)
+    beta = 1.7
+    S_ref = abelian_flux_action(L, F, beta, c1)
+    lat = Lattice(L, 1)
+    g = din.random_su3(lat.shape4, 1.0, 121)
+    Ug = gauge_transform(lat, U, g)
+    for V in (U, Ug):
+        assert oracle.gauge_action(V, beta, c1) == pytest.approx(S_ref, rel=1e-12)
+        assert np.abs(oracle.gauge_force(V, beta, c1)).max() < 1e-12 * beta * lat.V
+    # a non-uniform field is not stationary: the vanishing above is not trivial
+    U2 = U.copy()
+    U2[1, 0, 0, 0, 0] = din.random_su3((), 0.5, 122) @ U2[1, 0, 0, 0, 0]
+    assert np.abs(oracle.gauge_force(U2, beta, c1)).max() > 1e-2
+
+
+@pytest.mark.parametrize("c1", [0.0, oracle.IWASAKI_C1])
+def test_gauge_invariance_and_covariance(c1):
+    lat = Lattice((4, 2, 4, 6), 1)
+    U = din.random_gauge(lat.L, 0.6, 123)
+    g = din.random_su3(lat.shape4, 1.0, 124)
+    Ug = gauge_transform(lat, U, g)
+    assert oracle.gauge_action(Ug, 2.0, c1) == pytest.approx(oracle.gauge_action(U, 2.0, c1), rel=1e-13)
+    F, Fg = oracle.gauge_force(U, 2.0, c1), oracle.gauge_force(Ug, 2.0, c1)
+    assert np.abs(Fg - g @ F @ np.swapaxes(g.conj(), -1, -2)).max() < 1e-12
+    # traceless Hermitian
+    assert np.abs(F - np.swapaxes(F.conj(), -1, -2)).max() < 1e-14
+    assert np.abs(np.trace(F, axis1=-2, axis2=-1)).max() < 1e-13
+
+
+@pytest.mark.parametrize("c1", [0.0, oracle.IWASAKI_C1])
+def test_gauge_force_finite_difference(c1):
+    """d^a S_g = 2 tr(T^a F) against Richardson-extrapolated central
+    differences along U_mu(x) -> exp(i eps T^a) U_mu(x)."""
+    lat = Lattice((4, 4, 2, 6), 1)
+    U = din.random_gauge(lat.L, 0.7, 125)
+    beta = 2.25
+    F = oracle.gauge_force(U, beta, c1)
+    T = din.gell_mann() / 2
+    r = np.random.default_rng(126)
+    for _ in range(6):
+        mu = int(r.integers(4))
+        site = tuple(int(r.integers(n)) for n in lat.shape4)
+        a = int(r.integers(8))
+
+        def S_at(e):
+            V = U.copy()
+            V[(mu,) + site] = oracle.expi_hermitian(e * T[a]) @ V[(mu,) + site]
+            return oracle.gauge_action(V, beta, c1)
+
+        h = 1e-3
+        d1 = (S_at(h) - S_at(-h)) / (2 * h)
+        d2 = (S_at(h / 2) - S_at(-h / 2)) / h
+        fd = (4 * d2 - d1) / 3
+        an = 2 * np.trace(T[a] @ F[(mu,) + site]).real
+        assert an == pytest.approx(fd, rel=1e-7, abs=1e-8)
