@@ -211,11 +211,33 @@ int eofa_force(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
 int eofa_md_update(eofa_ctx_t *ctx, void *U_dev, void *P_dev, const void *F_dev,
                    double dt_p, double dt_u, double *kinetic_out);
 
+/* Gauge action of the ensembles the paper runs on (Table 1: Iwasaki), FP64:
+ *   S_g = beta sum_x [ c0 sum_{mu<nu} (1 - Re tr W_1x1(x)/3)
+ *                    + c1 sum_{mu!=nu} (1 - Re tr W_2x1(x)/3) ],  c0 = 1 - 8 c1,
+ * W_1x1 the plaquette in the (mu, nu) plane at x and W_2x1 the loop two
+ * links long in mu and one in nu.  c1 = -0.331: Iwasaki (the paper names the
+ * action, not its coefficients); c1 = 0: Wilson.  Links are periodic in
+ * every direction.
+ * U_dev: any gauge field in the natural gauge layout (not necessarily the
+ *        context's own copy); only the context's geometry and stream are used.
+ * S_out: the action (host).  Synchronises the stream.
+ * Errors: EOFA_EINVAL (NULL, non-finite beta or c1), EOFA_ENAN. */
+int eofa_gauge_action(eofa_ctx_t *ctx, const void *U_dev, double beta, double c1, double *S_out);
+
+/* Force of the gauge action above, in the convention of eofa_force:
+ * F_mu(x) = sum_a T^a d^a S_g (Hermitian traceless 3x3 per link, gauge
+ * layout), d^a along U_mu(x) -> exp(i eps T^a) U_mu(x), T^a = lambda^a/2.
+ * accumulate = 0: F_dev = F_g; otherwise F_dev += F_g (to add the gauge
+ * force to a fermion force).  F_dev must not alias U_dev.  Asynchronous
+ * on the context stream.  Errors: EOFA_EINVAL (NULL, aliasing, non-finite). */
+int eofa_gauge_force(eofa_ctx_t *ctx, const void *U_dev, double beta, double c1, void *F_dev, int accumulate);
+
 /* Per-kernel timing with HIP events on the context stream.
  * eofa_timing_enable(ctx, 1) starts recording (and clears totals);
  * eofa_timing_query synchronises and returns, for kernel class `name`
  * ("hop" = the 5D hopping kernel in any precision, "hop64", "hop32",
- * "hop16", "hopb16", "blas", "force", "md"), the launch count, the summed
+ * "hop16", "hopb16", "blas", "force", "md", "gauge_force",
+ * "gauge_action"), the launch count, the summed
  * duration in ms and the summed algorithmic bytes. */
 int eofa_timing_enable(eofa_ctx_t *ctx, int on);
 int eofa_timing_query(eofa_ctx_t *ctx, const char *name, long *count, double *ms, double *bytes);

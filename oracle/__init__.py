@@ -413,6 +413,47 @@ def gauge_force(U, beta, c1=IWASAKI_C1):
     return -(beta / 12.0) * (Y - tr * np.eye(3))
 
 
+def path_product_at(U, steps, site, start=(0, 0, 0, 0)):
+    """path_product at one site (t, z, y, x) only: the same walk, with the
+    coordinates wrapped by hand instead of rolled fields."""
+    ext = U.shape[1:5]                         # (Lt, Lz, Ly, Lx)
+    z = [int(v) for v in site]
+    for mu in range(4):
+        z[3 - mu] = (z[3 - mu] + start[mu]) % ext[3 - mu]
+    M = np.eye(3, dtype=np.complex128)
+    for st in steps:
+        mu = abs(st) - 1
+        if st > 0:
+            M = M @ U[(mu,) + tuple(z)]
+            z[3 - mu] = (z[3 - mu] + 1) % ext[3 - mu]
+        else:
+            z[3 - mu] = (z[3 - mu] - 1) % ext[3 - mu]
+            M = M @ U[(mu,) + tuple(z)].conj().T
+    return M
+
+
+def gauge_force_at(U, beta, c1, links):
+    """gauge_force at the listed links (mu, t, z, y, x) only (for lattices
+    too large for the whole-field version); returns (len(links), 3, 3)."""
+    out = np.empty((len(links), 3, 3), dtype=np.complex128)
+    loops = gauge_loops(c1)
+    for n, (mu, *site) in enumerate(links):
+        e = [0, 0, 0, 0]
+        e[mu] = 1
+        sig = np.zeros((3, 3), dtype=np.complex128)
+        for c, steps in loops:
+            rev = [-st for st in reversed(steps)]
+            for loop in (steps, rev):
+                for k in range(len(loop)):
+                    rot = loop[k:] + loop[:k]
+                    if rot[0] == mu + 1:
+                        sig += c * path_product_at(U, rot[1:], site, start=e)
+        Om = U[(mu,) + tuple(site)] @ sig
+        Y = 1j * (Om - Om.conj().T)
+        out[n] = -(beta / 12.0) * (Y - np.trace(Y) / 3.0 * np.eye(3))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # heatbath (Section 3.2, eq. (3.1)) -- plain numpy on top of H_op
 # ---------------------------------------------------------------------------

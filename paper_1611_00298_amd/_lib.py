@@ -17,7 +17,7 @@ PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 EXPORTS = [
     "eofa_ctx_create", "eofa_ctx_destroy", "eofa_ctx_update_gauge", "dwf_apply", "eofa_solve",
     "eofa_force", "eofa_md_update", "eofa_rational_inv_sqrt", "eofa_heatbath", "eofa_meofa_bounds", "eofa_chrono",
-    "eofa_timing_enable",
+    "eofa_gauge_action", "eofa_gauge_force", "eofa_timing_enable",
     "eofa_timing_query", "eofa_last_error",
 ]
 
@@ -74,6 +74,8 @@ def load() -> C.CDLL:
         "eofa_chrono": (I_, [P, I_]),
         "eofa_meofa_bounds": (I_, [P, D, D, P, I_, C.POINTER(Solver), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(Stats)]),
+        "eofa_gauge_action": (I_, [P, P, D, D, C.POINTER(C.c_double)]),
+        "eofa_gauge_force": (I_, [P, P, D, D, P, I_]),
         "eofa_timing_enable": (I_, [P, I_]),
         "eofa_timing_query": (I_, [P, C.c_char_p, C.POINTER(C.c_long), C.POINTER(C.c_double),
                                    C.POINTER(C.c_double)]),

@@ -15,6 +15,9 @@ import torch
 from . import _lib
 from ._lib import PREC, Geom, Solver, Stats, check
 
+# Iwasaki rectangle coefficient (the gauge action of Table 1); c0 = 1 - 8 c1
+IWASAKI_C1 = -0.331
+
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
@@ -212,6 +215,26 @@ class Context:
                                       float(dt_u), C.byref(kin)))
         return kin.value
 
+    # -- gauge action (Table 1: Iwasaki; c1 = 0 is Wilson) -----------------------
+    def gauge_action(self, U, beta, c1=IWASAKI_C1):
+        """S_g of the field U (any field of this geometry), FP64."""
+        _want(U, self.shape_gauge, "U")
+        S = C.c_double(0.0)
+        check(self.lib.eofa_gauge_action(self.handle, _ptr(U), float(beta), float(c1), C.byref(S)))
+        return S.value
+
+    def gauge_force(self, U, beta, c1=IWASAKI_C1, out=None, accumulate=False):
+        """F_g = sum_a T^a d^a S_g of U; with accumulate, out += F_g."""
+        _want(U, self.shape_gauge, "U")
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs out")
+            out = torch.empty_like(U)
+        _want(out, self.shape_gauge, "out")
+        check(self.lib.eofa_gauge_force(self.handle, _ptr(U), float(beta), float(c1), _ptr(out),
+                                        int(bool(accumulate))))
+        return out
+
     # -- timing ------------------------------------------------------------------
     def timing_enable(self, on=True):
         check(self.lib.eofa_timing_enable(self.handle, int(bool(on))))
@@ -254,3 +277,11 @@ def eofa_force(ctx: Context, m1, m2, **kw):
 
 def eofa_md_update(ctx: Context, U, P, F=None, dt_p=0.0, dt_u=0.0):
     return ctx.md_update(U, P, F, dt_p, dt_u)
+
+
+def eofa_gauge_action(ctx: Context, U, beta, c1=IWASAKI_C1):
+    return ctx.gauge_action(U, beta, c1)
+
+
+def eofa_gauge_force(ctx: Context, U, beta, c1=IWASAKI_C1, out=None, accumulate=False):
+    return ctx.gauge_force(U, beta, c1, out, accumulate)

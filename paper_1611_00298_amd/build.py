@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libeofa.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["dslash.hip", "blas.hip", "fields.hip", "force.hip", "rational.cpp", "api.cpp"]
+SOURCES = ["dslash.hip", "blas.hip", "fields.hip", "force.hip", "gauge.hip", "rational.cpp", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EOFA_OFFLOAD_ARCH", "gfx950")

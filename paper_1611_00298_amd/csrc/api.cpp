@@ -77,6 +77,10 @@ hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, con
 int md_blocks(int nlink);
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st);
+int gauge_action_blocks(int V);
+hipError_t launch_gauge_force(const void* U, void* F, const int L[4], double beta, double c1, int accumulate,
+                              hipStream_t st);
+hipError_t launch_gauge_action(const void* U, const int L[4], double c1, double* partial, hipStream_t st);
 }  // namespace eofa
 
 using namespace eofa;
@@ -108,8 +112,9 @@ struct Half {
     int prec = -1;
 };
 
-enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_MD, C_NCLS };
-const char* cls_name[C_NCLS] = {"hop64", "hop32", "hop16", "hopb16", "blas", "force", "md"};
+enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_MD, C_GFORCE, C_GACTION, C_NCLS };
+const char* cls_name[C_NCLS] = {"hop64", "hop32", "hop16", "hopb16", "blas", "force", "md",
+                                "gauge_force", "gauge_action"};
 
 struct TimingRec {
     int cls;
@@ -1315,6 +1320,7 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             size_t np = (size_t)2 * c->nblk_hop;
             np = std::max(np, (size_t)action_blocks(c->V));
             np = std::max(np, (size_t)md_blocks(4 * c->V));
+            np = std::max(np, (size_t)gauge_action_blocks(c->V));
             np = std::max(np, (size_t)2 * c->nblk_blas);   // complex inner products
             c->npartial = np;
             hipchk(hipMalloc((void**)&c->partial, sizeof(double) * np), "hipMalloc(partial)");
@@ -1514,6 +1520,37 @@ int eofa_md_update(eofa_ctx_t* c, void* U, void* P, const void* F, double dt_p, 
             reduce(c, md_blocks(nlink), S_T1);
             *kin = read_slot(c, S_T1);
         }
+        return EOFA_OK;
+    });
+}
+
+int eofa_gauge_action(eofa_ctx_t* c, const void* U, double beta, double c1, double* S) {
+    return guarded([&]() -> int {
+        if (!c || !U || !S) fail(EOFA_EINVAL, "NULL argument");
+        if (!std::isfinite(beta) || !std::isfinite(c1)) fail(EOFA_EINVAL, "beta and c1 must be finite");
+        if (4.0 * c->V > 2147483647.0) fail(EOFA_EINVAL, "lattice too large for 32-bit link indices");
+        const int ev = timing_begin(c);
+        hipchk(launch_gauge_action(U, c->L, c1, c->partial, c->st), "gauge action");
+        // algorithmic bytes: every link read once
+        timing_end(c, ev, C_GACTION, 4.0 * c->V * 144.0);
+        reduce(c, gauge_action_blocks(c->V), S_T1);
+        const double s = read_slot(c, S_T1);
+        if (!std::isfinite(s)) fail(EOFA_ENAN, "gauge action is not finite");
+        *S = beta * s;
+        return EOFA_OK;
+    });
+}
+
+int eofa_gauge_force(eofa_ctx_t* c, const void* U, double beta, double c1, void* F, int accumulate) {
+    return guarded([&]() -> int {
+        if (!c || !U || !F) fail(EOFA_EINVAL, "NULL argument");
+        if (!std::isfinite(beta) || !std::isfinite(c1)) fail(EOFA_EINVAL, "beta and c1 must be finite");
+        if (4.0 * c->V > 2147483647.0) fail(EOFA_EINVAL, "lattice too large for 32-bit link indices");
+        if (U == F) fail(EOFA_EINVAL, "F must not alias U");
+        const int ev = timing_begin(c);
+        hipchk(launch_gauge_force(U, F, c->L, beta, c1, accumulate, c->st), "gauge force");
+        // algorithmic bytes: every link read once, F written (and read when accumulating)
+        timing_end(c, ev, C_GFORCE, 4.0 * c->V * 144.0 * (accumulate ? 3.0 : 2.0));
         return EOFA_OK;
     });
 }

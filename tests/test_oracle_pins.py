@@ -11,6 +11,7 @@ import scipy.linalg
 
 import dwf_inputs as din
 import oracle
+from helpers import abelian_flux_action, abelian_flux_field
 from oracle import Lattice
 
 
@@ -625,42 +626,6 @@ def test_heatbath_draws_from_M_eofa(dense_heatbath):
 # P12: gauge action of the ensembles (Table 1: Iwasaki; c1 = 0 is Wilson)
 # --------------------------------------------------------------------------
 
-def abelian_flux_field(L, quanta):
-    """U(1) links embedded as diag(e^{i th}, e^{-i th}, 1) with a uniform flux
-    F_{mu nu} = 2 pi n_{mu nu} / (L_mu L_nu) through every plaquette of each
-    plane on the periodic lattice ('t Hooft's twisted construction):
-    th_nu(x) = sum_{mu<nu} F_{mu nu} x_mu, and on the last slice x_mu = L_mu - 1
-    th_mu also carries -sum_{nu>mu} F_{mu nu} L_mu x_nu."""
-    shape4 = (L[3], L[2], L[1], L[0])
-    t, z, y, x = np.indices(shape4)
-    X = (x, y, z, t)
-    F = {}
-    th = np.zeros((4,) + shape4)
-    for (mu, nu), n in quanta.items():
-        F[mu, nu] = 2 * np.pi * n / (L[mu] * L[nu])
-        th[nu] += F[mu, nu] * X[mu]
-        th[mu] -= np.where(X[mu] == L[mu] - 1, F[mu, nu] * L[mu] * X[nu], 0.0)
-    U = np.zeros((4,) + shape4 + (3, 3), dtype=np.complex128)
-    U[..., 0, 0] = np.exp(1j * th)
-    U[..., 1, 1] = np.exp(-1j * th)
-    U[..., 2, 2] = 1.0
-    return U, F
-
-
-def abelian_flux_action(L, F, beta, c1):
-    """Closed form of S_g for the uniform-flux field: a loop enclosing flux
-    Phi has Re tr W / 3 = (2 cos Phi + 1)/3; a plane holds one plaquette
-    (flux F) and two rectangles (flux 2F, both orientations) per site."""
-    V = L[0] * L[1] * L[2] * L[3]
-    c0 = 1 - 8 * c1
-    S = 0.0
-    for mu in range(4):
-        for nu in range(mu + 1, 4):
-            f = F.get((mu, nu), 0.0)
-            S += c0 * (1 - (2 * np.cos(f) + 1) / 3) + 2 * c1 * (1 - (2 * np.cos(2 * f) + 1) / 3)
-    return beta * V * S
-
-
 @pytest.mark.parametrize("c1", [0.0, oracle.IWASAKI_C1])
 def test_gauge_unit_field(c1):
     lat = Lattice((4, 4, 4, 6), 1)
@@ -731,3 +696,17 @@ def test_gauge_force_finite_difference(c1):
         fd = (4 * d2 - d1) / 3
         an = 2 * np.trace(T[a] @ F[(mu,) + site]).real
         assert an == pytest.approx(fd, rel=1e-7, abs=1e-8)
+
+
+def test_gauge_force_pointwise_matches_field():
+    """The pointwise walk (used at full lattice size) equals the pinned
+    whole-field force, including links on the wrapped boundary."""
+    lat = Lattice((4, 2, 6, 4), 1)
+    U = din.random_gauge(lat.L, 0.7, 127)
+    F = oracle.gauge_force(U, 1.9, oracle.IWASAKI_C1)
+    r = np.random.default_rng(128)
+    links = [(int(r.integers(4)),) + tuple(int(r.integers(n)) for n in lat.shape4) for _ in range(12)]
+    links += [(0, 3, 5, 1, 3), (3, 3, 0, 0, 0)]
+    Fp = oracle.gauge_force_at(U, 1.9, oracle.IWASAKI_C1, links)
+    for n, l in enumerate(links):
+        assert np.abs(Fp[n] - F[l]).max() < 1e-13
