@@ -23,7 +23,9 @@ Other modes, each printing its own JSON line instead:
   --dslash      the hopping kernel's rate in all four precisions
   --trajectory  the 24^3x64 leapfrog trajectory, mixed vs FP64 (dH, reversibility)
   --heatbath    the eq. (3.1) heatbath: Lanczos interval, Zolotarev poles, 2 N_p solves
-  --hmc         one full trajectory (heatbath, force-gradient MD, energies) by phase
+  --hmc         one full trajectory (heatbath, force-gradient MD, energies) by phase;
+                --gauge-beta adds the Iwasaki gauge action on an inner time scale
+  --gauge       the gauge force and action kernels (Iwasaki and Wilson)
 """
 from __future__ import annotations
 
@@ -184,6 +186,63 @@ def dslash(args):
     return 0
 
 
+# FP64 flops of the gauge kernels (3x3 complex product: 27 complex
+# multiplications, 6 flops each, and 18 complex additions, 2 flops each = 198;
+# Re tr(a b^dag): 36; a scaled or accumulated matrix: 18 or 36)
+GAUGE_FORCE_FLOPS = {"iwasaki": 3 * (22 * 198 + 324) + 198 + 60, "wilson": 3 * (4 * 198 + 108) + 198 + 60}
+GAUGE_ACTION_FLOPS = {"iwasaki": 6 * (2 * 198 + 36) + 12 * (4 * 198 + 36), "wilson": 6 * (2 * 198 + 36)}
+FP64_PEAK_TFLOPS = 78.6
+
+
+def gauge(args):
+    """The gauge action of Table 1's ensembles (Iwasaki, c1 = -0.331; Wilson,
+    c1 = 0) and its force on the workload's links: 20 force and 5 action
+    launches per action after 3 untimed ones, HIP events on the context
+    stream.  Prints one JSON line with the average launch time, the
+    algorithmic HBM rate (links read once, F written once) and the FP64 rate
+    of each kernel."""
+    import torch
+    import dwf_inputs as din
+    from paper_1611_00298_amd import IWASAKI_C1, Context
+
+    pre = din.preset(args.workload)
+    dev = torch.device("cuda:0")
+    log(f"gauge: generating {args.workload} links")
+    U = torch.from_numpy(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"])).to(dev)
+    V = pre["L"][0] * pre["L"][1] * pre["L"][2] * pre["L"][3]
+    ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
+    F = torch.empty_like(U)
+    out = {"metric": "gauge force and action: ms per launch, GB/s and FP64 TFLOP/s (1 GPU)",
+           "config": {"workload": f"{'x'.join(map(str, pre['L']))} links, beta = 2.13"}, "actions": {}}
+    for name, c1 in (("iwasaki", IWASAKI_C1), ("wilson", 0.0)):
+        for _ in range(3):
+            ctx.gauge_force(U, 2.13, c1, out=F)
+            ctx.gauge_action(U, 2.13, c1)
+        torch.cuda.synchronize()
+        ctx.timing_enable(True)
+        for _ in range(20):
+            ctx.gauge_force(U, 2.13, c1, out=F)
+        S = 0.0
+        for _ in range(5):
+            S = ctx.gauge_action(U, 2.13, c1)
+        res = {"S": S}
+        for kern, units, flops in (("gauge_force", 4 * V, GAUGE_FORCE_FLOPS[name]),
+                                   ("gauge_action", V, GAUGE_ACTION_FLOPS[name])):
+            q = ctx.timing_query(kern)
+            ms = q["ms"] / q["count"]
+            res[kern] = {"launches": q["count"], "avg_ms": ms,
+                         "achieved_GBs": q["bytes"] / q["count"] / (ms * 1e-3) / 1e9,
+                         "flops_per_unit": flops,
+                         "tflops": units * flops / (ms * 1e-3) / 1e12,
+                         "frac_fp64": units * flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+            log(f"gauge {name} {kern}: {ms:.3f} ms, {res[kern]['tflops']:.1f} TFLOP/s")
+        ctx.timing_enable(False)
+        out["actions"][name] = res
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def trajectory(args):
     """The 24^3x64, Ls = 24 trajectory workload (c5): a fermion-only EOFA
     leapfrog trajectory of n_steps x dt from seeded links, pseudofermion and
@@ -216,11 +275,11 @@ def trajectory(args):
         U, P = U0.clone(), P0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+        H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
         prog = lambda i, st, lab=label: log(f"trajectory {lab}: force {i}: iters {st['iters']} "
                                             f"solve {st['seconds']:.2f}s")
         leapfrog(ctx, U, P, phi, m1, m2, n, dt, progress=prog, **solver)
-        H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+        H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         log(f"trajectory {label}: H0 {H0:.6f} H1 {H1:.6f} dH {H1 - H0:.6e} ({sec:.1f} s)")
@@ -348,8 +407,11 @@ def heatbath_cpu_baseline(solver):
 
 
 def hmc(args):
-    """One complete fermion-only EOFA HMC trajectory on the 24^3x64, Ls = 24
-    trajectory workload, timed by phase in the rows of Table 4: M_EOFA's
+    """One complete EOFA HMC trajectory on the 24^3x64, Ls = 24 trajectory
+    workload (fermion-only, or with the Iwasaki gauge action at
+    args.gauge_beta > 0 on args.n_gauge inner force-gradient steps per link
+    update), timed by phase in the
+    rows of Table 4: M_EOFA's
     interval (Lanczos) and the heatbath of eq. (3.1) with chronological
     guesses, the force-gradient QPQPQ integration (args.md_steps steps over
     unit trajectory length, four force evaluations per step), the final
@@ -357,7 +419,7 @@ def hmc(args):
     import numpy as np
     import torch
     import dwf_inputs as din
-    from paper_1611_00298_amd import Context, rational_inv_sqrt
+    from paper_1611_00298_amd import IWASAKI_C1, Context, rational_inv_sqrt
     from paper_1611_00298_amd.hmc import force_gradient, hamiltonian
 
     pre = din.preset("c5")
@@ -372,6 +434,7 @@ def hmc(args):
     P = t(din.gaussian_momenta(pre["L"], pre["seed_mom"]))
     ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
     solver = dict(tol=1e-10, inner=args.inner, reliable_delta=args.delta)
+    gauge = (args.gauge_beta, IWASAKI_C1) if args.gauge_beta > 0 else None
     sync = torch.cuda.synchronize
     sync()
     t0 = time.perf_counter()
@@ -392,7 +455,8 @@ def hmc(args):
     prog = lambda i, st: log(f"hmc: force {i}: iters {st['iters']} solve {st['seconds']:.2f}s")
     t0 = time.perf_counter()
     ctx.chrono(args.chrono)
-    fst = force_gradient(ctx, U, P, phi, m1, m2, n, dt, progress=prog, **solver)
+    fst = force_gradient(ctx, U, P, phi, m1, m2, n, dt, progress=prog, gauge=gauge, n_gauge=args.n_gauge,
+                         **solver)
     sync()
     t_md = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -403,12 +467,15 @@ def hmc(args):
     ctx.close()
     total = t_int + t_hb + t_h0 + t_md + t_h1
     dH = H1 - H0
-    out = {"metric": "fermion-only EOFA HMC trajectory: time by phase (Table 4 rows), 1 GPU",
+    kind = "fermion-only" if gauge is None else "EOFA + Iwasaki gauge"
+    out = {"metric": f"{kind} EOFA HMC trajectory: time by phase (Table 4 rows), 1 GPU",
            "value": total, "unit": "s", "higher_is_better": False,
            "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
                                   f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}: heatbath + {n} "
                                   f"force-gradient QPQPQ steps, tau = 1, solves to 1e-10",
-                      "inner_precision": args.inner},
+                      "inner_precision": args.inner,
+                      "gauge": None if gauge is None else {"beta": gauge[0], "c1": gauge[1],
+                                                           "inner_force_gradient_steps": args.n_gauge}},
            "data": "synthetic (random SU(3) links exp(i eps H), Gaussian eta and momenta)",
            "phases_s": {"interval_lanczos": t_int, "heatbath": t_hb, "initial_H": t_h0,
                         "force_gradient_integration": t_md, "final_H": t_h1},
@@ -418,7 +485,8 @@ def hmc(args):
                         "S0_over_eta2_minus_1": S0 / ee - 1.0},
            "md": {"force_evaluations": len(fst), "chrono": args.chrono, "solve_iters_total": [sum(s["iters"][0] for s in fst),
                                                                         sum(s["iters"][1] for s in fst)]},
-           "dH": dH, "H0": H0, "accept_probability": float(min(1.0, np.exp(-dH)))}
+           "dH": dH, "H0": H0, "S_gauge": [H0 - S0 - K0, H1 - S1 - K1],
+           "accept_probability": float(min(1.0, np.exp(-dH)))}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -449,8 +517,14 @@ def main():
                     help="instead of the step benchmark: one full EOFA HMC trajectory (heatbath, force-gradient "
                          "integration, energies) on the 24^3x64 trajectory workload, timed by phase")
     ap.add_argument("--md-steps", type=int, default=12, help="hmc: force-gradient steps per unit trajectory")
+    ap.add_argument("--gauge-beta", type=float, default=0.0,
+                    help="hmc: add the Iwasaki gauge action at this beta (0: fermion-only; Table 1's 24ID: 1.633)")
+    ap.add_argument("--n-gauge", type=int, default=2,
+                    help="hmc: inner force-gradient steps of the gauge dynamics per link update")
     ap.add_argument("--chrono", type=int, default=8,
                     help="hmc: earlier solutions per system for chronological guesses in the MD (0: none)")
+    ap.add_argument("--gauge", action="store_true",
+                    help="time the Iwasaki and Wilson gauge force and action kernels")
     ap.add_argument("--dslash", action="store_true",
                     help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -469,6 +543,8 @@ def main():
         return hmc(args)
     if args.dslash:
         return dslash(args)
+    if args.gauge:
+        return gauge(args)
 
     import torch
     import dwf_inputs as din

@@ -1,11 +1,25 @@
-"""Fermion-only EOFA hybrid Monte Carlo (Section 3).
+"""EOFA hybrid Monte Carlo (Section 3), optionally with the gauge action.
 
-H = sum tr P^2 + S_EOFA(U).  A trajectory draws phi = M_EOFA^(-1/2) eta by
-the rational heatbath of eq. (3.1), integrates the molecular dynamics, and
-accepts or rejects by Metropolis.  Each force evaluation is two Cayley-form
-CG solves plus the eq. (3.2) force kernel; the momentum and link updates
-run in FP64 in eofa_md_update.  The caller draws every random number
-(eta, the momenta, the Metropolis uniform); this module draws none.
+H = sum tr P^2 + S_EOFA(U) [+ S_g(U)].  A trajectory draws
+phi = M_EOFA^(-1/2) eta by the rational heatbath of eq. (3.1), integrates
+the molecular dynamics, and accepts or rejects by Metropolis.  Each fermion
+force evaluation is two Cayley-form CG solves plus the eq. (3.2) force
+kernel; the momentum and link updates run in FP64 in eofa_md_update.
+
+gauge = (beta, c1) adds the gauge action of Table 1's ensembles (Iwasaki:
+c1 = -0.331; Wilson: c1 = 0).  With n_gauge = 0 its force joins the fermion
+force at every evaluation (one time scale); with n_gauge >= 1 every link
+update U <- exp(i t P) U of the outer integrator becomes n_gauge steps of
+the gauge dynamics over t (two time scales: the cheap gauge force on the
+fine one), force-gradient steps by default (gauge_scheme) or leapfrog.
+Off equilibrium the gauge force is large and its energy error grows with
+the volume, so the fourth-order inner step pays for its four gauge-force
+evaluations.  The force-gradient displacement then uses the fermion
+force only: the gauge force, a function of the links alone, commutes with
+it in the step's commutator terms.
+
+The caller draws every random number (eta, the momenta, the Metropolis
+uniform); this module draws none.
 """
 from __future__ import annotations
 
@@ -14,35 +28,102 @@ import math
 from .api import Context
 
 
-def hamiltonian(ctx: Context, U, P, phi, m1, m2, **solver):
+def hamiltonian(ctx: Context, U, P, phi, m1, m2, gauge=None, **solver):
+    """(H, S_EOFA, sum tr P^2, solver statistics); H includes S_g when
+    gauge = (beta, c1) is given."""
     ctx.update_gauge(U)
     _, _, _, S, st = ctx.eofa_solve(phi, m1, m2, want_mphi=False, **solver)
     kin = ctx.md_update(U, P)            # dt = 0: only the kinetic term
-    return kin + S, S, kin, st
+    Sg = ctx.gauge_action(U, *gauge) if gauge is not None else 0.0
+    return kin + S + Sg, S, kin, st
 
 
-def leapfrog(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, **solver):
-    """In-place leapfrog trajectory; returns per-step statistics.
-    progress(i, stats), if given, is called after force evaluation i."""
-    stats = []
+class _Forces:
+    """Fermion (+ gauge) force evaluations and link updates shared by the
+    integrators (see the module docstring for the two gauge schemes)."""
 
-    def force():
-        ctx.update_gauge(U)
-        F, _, st = ctx.eofa_force(m1, m2, phi=phi, **solver)
-        stats.append(st)
-        if progress is not None:
-            progress(len(stats) - 1, st)
+    def __init__(self, ctx, phi, m1, m2, gauge, n_gauge, gauge_scheme, progress, solver):
+        if n_gauge < 0:
+            raise ValueError("n_gauge must be >= 0")
+        if gauge_scheme not in ("force_gradient", "leapfrog"):
+            raise ValueError("gauge_scheme is 'force_gradient' or 'leapfrog'")
+        self.gauge_scheme = gauge_scheme
+        self.Ud = self.Z = None
+        self.ctx, self.phi, self.m1, self.m2 = ctx, phi, m1, m2
+        self.gauge, self.n_gauge = gauge, int(n_gauge) if gauge is not None else 0
+        self.progress, self.solver = progress, solver
+        self.stats = []
+        self.Fg = None
+
+    def force(self, Ux):
+        """Outer force at links Ux: the fermion force, plus the gauge force
+        when it lives on the same time scale."""
+        ctx = self.ctx
+        ctx.update_gauge(Ux)
+        F, _, st = ctx.eofa_force(self.m1, self.m2, phi=self.phi, **self.solver)
+        if self.gauge is not None and self.n_gauge == 0:
+            ctx.gauge_force(Ux, *self.gauge, out=F, accumulate=True)
+        self.stats.append(st)
+        if self.progress is not None:
+            self.progress(len(self.stats) - 1, st)
         return F
 
-    F = force()
-    ctx.md_update(U, P, F, dt_p=0.5 * dt, dt_u=dt)
+    def links(self, U, P, t):
+        """U <- exp(i t P) U, or n_gauge leapfrog steps of the gauge
+        dynamics over t on the inner time scale."""
+        ctx = self.ctx
+        if t == 0.0:
+            return
+        if self.n_gauge == 0:
+            ctx.md_update(U, P, None, dt_p=0.0, dt_u=t)
+            return
+        h = t / self.n_gauge
+        if self.Fg is None:
+            self.Fg = ctx.gauge_force(U, *self.gauge)
+        if self.gauge_scheme == "leapfrog":
+            ctx.gauge_force(U, *self.gauge, out=self.Fg)
+            for _ in range(self.n_gauge):
+                ctx.md_update(U, P, self.Fg, dt_p=0.5 * h, dt_u=h)
+                ctx.gauge_force(U, *self.gauge, out=self.Fg)
+                ctx.md_update(U, P, self.Fg, dt_p=0.5 * h, dt_u=0.0)
+            return
+        for _ in range(self.n_gauge):   # force-gradient QPQPQ on the gauge force alone
+            ctx.md_update(U, P, None, dt_p=0.0, dt_u=FG_LAMBDA * h)
+            self._gauge_kick(U, P, h)
+            ctx.md_update(U, P, None, dt_p=0.0, dt_u=(1.0 - 2.0 * FG_LAMBDA) * h)
+            self._gauge_kick(U, P, h)
+            ctx.md_update(U, P, None, dt_p=0.0, dt_u=FG_LAMBDA * h)
+
+    def _gauge_kick(self, U, P, h):
+        """P <- P - (h/2) F_g(U'), U' = exp(-i xi h^2 F_g(U)) U."""
+        import torch
+        ctx = self.ctx
+        if self.Ud is None:
+            self.Ud, self.Z = torch.empty_like(U), torch.empty_like(P)
+        ctx.gauge_force(U, *self.gauge, out=self.Fg)
+        self.Ud.copy_(U)
+        self.Z.zero_()
+        ctx.md_update(self.Ud, self.Z, self.Fg, dt_p=FG_XI * h * h, dt_u=1.0)
+        ctx.gauge_force(self.Ud, *self.gauge, out=self.Fg)
+        ctx.md_update(U, P, self.Fg, dt_p=0.5 * h, dt_u=0.0)
+
+
+def leapfrog(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, gauge=None, n_gauge=0,
+             gauge_scheme="force_gradient", **solver):
+    """In-place leapfrog trajectory; returns per-step statistics.
+    progress(i, stats), if given, is called after force evaluation i."""
+    fs = _Forces(ctx, phi, m1, m2, gauge, n_gauge, gauge_scheme, progress, solver)
+    F = fs.force(U)
+    ctx.md_update(U, P, F, dt_p=0.5 * dt, dt_u=0.0)
+    fs.links(U, P, dt)
     for step in range(1, n_steps):
-        F = force()
-        ctx.md_update(U, P, F, dt_p=dt, dt_u=dt)
-    F = force()
+        F = fs.force(U)
+        ctx.md_update(U, P, F, dt_p=dt, dt_u=0.0)
+        fs.links(U, P, dt)
+    F = fs.force(U)
     ctx.md_update(U, P, F, dt_p=0.5 * dt, dt_u=0.0)
     ctx.update_gauge(U)
-    return stats
+    return fs.stats
 
 
 # Force-gradient QPQPQ step (the integrator family of Section 5):
@@ -60,40 +141,34 @@ FG_LAMBDA = (3.0 - math.sqrt(3.0)) / 6.0
 FG_XI = (2.0 - math.sqrt(3.0)) / 12.0
 
 
-def force_gradient(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, **solver):
+def force_gradient(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, gauge=None, n_gauge=0,
+                   gauge_scheme="force_gradient", **solver):
     """In-place force-gradient QPQPQ trajectory of n_steps x dt; returns the
     per-force-evaluation statistics.  progress(i, stats) as in leapfrog."""
     import torch
-    stats = []
-
-    def force(Ux):
-        ctx.update_gauge(Ux)
-        F, _, st = ctx.eofa_force(m1, m2, phi=phi, **solver)
-        stats.append(st)
-        if progress is not None:
-            progress(len(stats) - 1, st)
-        return F
+    fs = _Forces(ctx, phi, m1, m2, gauge, n_gauge, gauge_scheme, progress, solver)
 
     def kick():
-        F = force(U)
+        F = fs.force(U)
         Ud = U.clone()
         Z = torch.zeros_like(P)
         ctx.md_update(Ud, Z, F, dt_p=FG_XI * dt * dt, dt_u=1.0)   # Z = -xi h^2 F, Ud = e^{iZ} U
-        ctx.md_update(U, P, force(Ud), dt_p=0.5 * dt, dt_u=0.0)
+        ctx.md_update(U, P, fs.force(Ud), dt_p=0.5 * dt, dt_u=0.0)
 
-    ctx.md_update(U, P, None, dt_p=0.0, dt_u=FG_LAMBDA * dt)
+    fs.links(U, P, FG_LAMBDA * dt)
     for step in range(n_steps):
         kick()
-        ctx.md_update(U, P, None, dt_p=0.0, dt_u=(1.0 - 2.0 * FG_LAMBDA) * dt)
+        fs.links(U, P, (1.0 - 2.0 * FG_LAMBDA) * dt)
         kick()
         last = step == n_steps - 1   # adjacent link updates of two steps merge
-        ctx.md_update(U, P, None, dt_p=0.0, dt_u=(1.0 if last else 2.0) * FG_LAMBDA * dt)
+        fs.links(U, P, (1.0 if last else 2.0) * FG_LAMBDA * dt)
     ctx.update_gauge(U)
-    return stats
+    return fs.stats
 
 
 def trajectory(ctx: Context, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_accept=None,
-               integrator=None, progress=None, chrono=0, **solver):
+               integrator=None, progress=None, chrono=0, gauge=None, n_gauge=0,
+               gauge_scheme="force_gradient", **solver):
     """One HMC trajectory from links U and fresh momenta P (both updated in
     place; restored on rejection):
     phi = M_EOFA^(-1/2) eta (eq. (3.1), Zolotarev on [lo, hi] with n_poles),
@@ -101,21 +176,23 @@ def trajectory(ctx: Context, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_
     (default) or force_gradient), H1, then accept if u_accept < exp(-(H1 - H0)) (always accept
     when u_accept is None).  chrono > 0 starts the molecular-dynamics solves
     from chronological guesses over the last `chrono` solutions (history
-    cleared here, since phi is new).  Returns a dict with H0, dH, accepted
-    and the heatbath and force statistics."""
+    cleared here, since phi is new).  gauge = (beta, c1), n_gauge and
+    gauge_scheme add the gauge action (module docstring).  Returns a dict with H0, dH, accepted,
+    the fermion and gauge actions and the heatbath and force statistics."""
     ctx.update_gauge(U)
     phi, hb = ctx.eofa_heatbath(eta, m1, m2, lo=lo, hi=hi, n_poles=n_poles, **solver)
     ctx.chrono(chrono)
     U0, P0 = U.clone(), P.clone()
-    H0, S0, _, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+    H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
     step = integrator or leapfrog
-    st = step(ctx, U, P, phi, m1, m2, n_steps, dt, progress=progress, **solver)
-    H1, S1, _, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+    st = step(ctx, U, P, phi, m1, m2, n_steps, dt, progress=progress, gauge=gauge, n_gauge=n_gauge,
+              gauge_scheme=gauge_scheme, **solver)
+    H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
     dH = H1 - H0
     accepted = True if u_accept is None else bool(u_accept < math.exp(min(0.0, -dH)))
     if not accepted:
         U.copy_(U0)
         P.copy_(P0)
         ctx.update_gauge(U)
-    return {"H0": H0, "dH": dH, "S0": S0, "S1": S1, "accepted": accepted, "heatbath": hb,
-            "forces": st}
+    return {"H0": H0, "dH": dH, "S0": S0, "S1": S1, "Sg0": H0 - S0 - K0, "Sg1": H1 - S1 - K1,
+            "accepted": accepted, "heatbath": hb, "forces": st}

@@ -1,5 +1,5 @@
-"""EOFAAction (torch.autograd.Function) and the fermion-only EOFA molecular
-dynamics (Section 3) on the GPU."""
+"""EOFAAction (torch.autograd.Function) and the EOFA molecular dynamics
+(Section 3), with and without the gauge action, on the GPU."""
 import numpy as np
 import pytest
 
@@ -190,4 +190,107 @@ def test_chronological_guesses(c1):
     ctx.chrono(0)
     assert np.abs(res[6][0] - res[0][0]).max() < 1e-8
     assert res[6][1] < 0.8 * res[0][1], (res[0][1], res[6][1])
+    ctx.update_gauge(to_dev(U0))
+
+
+# 16I's gauge coupling (Table 1) with the Iwasaki coefficient
+GAUGE = (2.13, oracle.IWASAKI_C1)
+
+
+def test_force_gradient_with_gauge_action(c1):
+    """H = sum tr P^2 + S_EOFA + S_g.  One time scale (gauge force added to
+    the fermion force): still fourth order.  Two time scales (gauge force on
+    n_gauge inner leapfrog steps): refining the inner level shrinks |dH|, and
+    the scheme is reversible."""
+    from paper_1611_00298_amd.hmc import force_gradient, hamiltonian
+    lat, U0, phi, ctx = c1
+    m1, m2 = C1["m1"], C1["m2"]
+    P0 = din.gaussian_momenta(C1["L"], 311)
+    ph = to_dev(phi)
+    U, P = to_dev(U0), to_dev(P0)
+    H0, S0, K0, _ = hamiltonian(ctx, U, P, ph, m1, m2, gauge=GAUGE, tol=1e-12)
+    assert H0 - S0 - K0 == pytest.approx(oracle.gauge_action(U0, *GAUGE), rel=1e-10)
+
+    def run(n, dt, ng, scheme="force_gradient"):
+        U, P = to_dev(U0), to_dev(P0)
+        force_gradient(ctx, U, P, ph, m1, m2, n, dt, gauge=GAUGE, n_gauge=ng, gauge_scheme=scheme,
+                       tol=1e-12)
+        H1, _, _, _ = hamiltonian(ctx, U, P, ph, m1, m2, gauge=GAUGE, tol=1e-12)
+        return U, P, H1 - H0
+
+    _, _, d1 = run(2, 0.2, 0)
+    _, _, d2 = run(4, 0.1, 0)
+    assert abs(d2) > 1e-7 and 9.0 < abs(d1 / d2) < 28.0, (d1, d2)
+    # an inner leapfrog's error dominates dH here, and falls with n_gauge
+    _, _, e1 = run(2, 0.2, 1, "leapfrog")
+    _, _, e4 = run(2, 0.2, 4, "leapfrog")
+    assert abs(e4) < 0.25 * abs(e1), (e1, e4)
+    U, P, _ = run(2, 0.2, 2)
+    P.neg_()
+    force_gradient(ctx, U, P, ph, m1, m2, 2, 0.2, gauge=GAUGE, n_gauge=2, tol=1e-12)
+    assert np.abs(U.cpu().numpy() - U0).max() < 1e-10
+    assert np.abs(-P.cpu().numpy() - P0).max() < 1e-9
+    ctx.update_gauge(to_dev(U0))
+
+
+@pytest.mark.parametrize("scheme", ["force_gradient", "leapfrog"])
+def test_nested_gauge_level_matches_a_cpu_replay(c1, scheme):
+    """At m1 = m2 the EOFA force vanishes, so the two-time-scale
+    force-gradient trajectory is the pure-gauge integration of each
+    link-update segment (lambda h, (1 - 2 lambda) h, 2 lambda h, ...,
+    lambda h), n_gauge inner steps each: replayed on the CPU with the
+    oracle's force and update."""
+    from paper_1611_00298_amd.hmc import FG_LAMBDA, FG_XI, force_gradient
+    lat, U0, phi, ctx = c1
+    P0 = din.gaussian_momenta(C1["L"], 312)
+    n, dt, ng = 2, 0.2, 3
+    U, P = to_dev(U0), to_dev(P0)
+    force_gradient(ctx, U, P, to_dev(phi), 0.3, 0.3, n, dt, gauge=GAUGE, n_gauge=ng, gauge_scheme=scheme,
+                   tol=1e-10)
+    segs = [FG_LAMBDA * dt]
+    for s in range(n):
+        segs += [(1 - 2 * FG_LAMBDA) * dt, (1.0 if s == n - 1 else 2.0) * FG_LAMBDA * dt]
+    Fg = lambda X: oracle.gauge_force(X, *GAUGE)
+    drift = lambda X, Q, t: oracle.md_update(X, Q, Q, 0.0, t)
+    Uc, Pc = U0.copy(), P0.copy()
+    for t in segs:
+        h = t / ng
+        for _ in range(ng):
+            if scheme == "leapfrog":
+                Uc, Pc = oracle.md_update(Uc, Pc, Fg(Uc), 0.5 * h, h)
+                Pc = Pc - 0.5 * h * Fg(Uc)
+                continue
+            for a in (FG_LAMBDA, 1 - 2 * FG_LAMBDA):
+                Uc, Pc = drift(Uc, Pc, a * h)
+                Ud, _ = oracle.md_update(Uc, np.zeros_like(Pc), Fg(Uc), FG_XI * h * h, 1.0)
+                Pc = Pc - 0.5 * h * Fg(Ud)
+            Uc, Pc = drift(Uc, Pc, FG_LAMBDA * h)
+    assert np.abs(U.cpu().numpy() - Uc).max() < 1e-10
+    assert np.abs(P.cpu().numpy() - Pc).max() < 1e-9
+    ctx.update_gauge(to_dev(U0))
+
+
+def test_trajectory_with_gauge_action(c1):
+    """A full trajectory with the gauge action on two time scales: the
+    heatbath still gives S_EOFA(phi) = eta^dag eta, S_g is reported at both
+    ends, and |dH| stays well below 1."""
+    from paper_1611_00298_amd import rational_inv_sqrt
+    from paper_1611_00298_amd.hmc import force_gradient, trajectory
+    lat, U0, phi, ctx = c1
+    eta = din.gaussian_4d(C1["L"], 406)
+    P0 = din.gaussian_momenta(C1["L"], 313)
+    ee = float(np.vdot(eta, eta).real)
+    ctx.update_gauge(to_dev(U0))
+    tmin, tmax, rmin, rmax, _ = ctx.meofa_bounds(to_dev(eta), C1["m1"], C1["m2"], n_iter=30, tol=1e-10,
+                                                 inner="fp64")
+    lo, hi = 0.98 * (tmin - rmin), 1.02 * (tmax + rmax)
+    n_poles = next(n for n in range(1, 40) if rational_inv_sqrt(lo, hi, n)[3] < 1e-9)
+    U, P = to_dev(U0), to_dev(P0)
+    r = trajectory(ctx, U, P, to_dev(eta), C1["m1"], C1["m2"], 2, 0.1, lo=lo, hi=hi, n_poles=n_poles,
+                   u_accept=0.0, integrator=force_gradient, gauge=GAUGE, n_gauge=4, tol=1e-11)
+    assert abs(r["S0"] / ee - 1) < 1e-7
+    assert r["Sg0"] == pytest.approx(oracle.gauge_action(U0, *GAUGE), rel=1e-10)
+    assert r["Sg1"] == pytest.approx(oracle.gauge_action(U.cpu().numpy(), *GAUGE), rel=1e-10)
+    # rough synthetic fields: an inner leapfrog (n_gauge = 4) gave dH = -0.126 here
+    assert r["accepted"] and abs(r["dH"]) < 0.5, r["dH"]
     ctx.update_gauge(to_dev(U0))
