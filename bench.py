@@ -26,6 +26,7 @@ Other modes, each printing its own JSON line instead:
   --hmc         one full trajectory (heatbath, force-gradient MD, energies) by phase;
                 --gauge-beta adds the Iwasaki gauge action on an inner time scale
   --gauge       the gauge force and action kernels (Iwasaki and Wilson)
+  --dense       the EOFA solves on D_EOFA itself against the Cayley form (Table 4)
 """
 from __future__ import annotations
 
@@ -243,6 +244,63 @@ def gauge(args):
     return 0
 
 
+def dense(args):
+    """Table 4's comparison at the solve level: the two EOFA systems on the
+    workload solved (a) on D_EOFA itself, whose 5D structure is dense (FP64
+    even-odd CGNR), (b) in the Cayley form (FP64), (c) in the Cayley form with
+    the mixed-precision solver (args.inner), all to the same true residual
+    1e-10 of the same systems.  HIP-event timing of the hopping kernels.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+    import dwf_inputs as din
+    from paper_1611_00298_amd import Context
+
+    pre = din.preset(args.workload)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    log(f"dense: generating {args.workload} inputs")
+    U = t(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"]))
+    phi = t(din.gaussian_4d(pre["L"], pre["seed_phi"]))
+    m1, m2 = pre["m1"], pre["m2"]
+    ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
+    res, sols = {}, {}
+    runs = (("dense_fp64", lambda: ctx.eofa_solve_dense(phi, m1, m2, tol=1e-10, want_mphi=False)),
+            ("cayley_fp64", lambda: ctx.eofa_solve(phi, m1, m2, tol=1e-10, inner="fp64", want_mphi=False)),
+            (f"cayley_{args.inner}", lambda: ctx.eofa_solve(phi, m1, m2, tol=1e-10, inner=args.inner,
+                                                           reliable_delta=args.delta, want_mphi=False)))
+    for name, run in runs:
+        torch.cuda.synchronize()
+        ctx.timing_enable(True)
+        t0 = time.perf_counter()
+        chiL, chiR, _, S, st = run()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        cls = "hop64_dense" if name.startswith("dense") else "hop"
+        q = ctx.timing_query(cls)
+        ctx.timing_enable(False)
+        sols[name] = (chiL, chiR)
+        res[name] = {"seconds": sec, "iters": st["iters"], "true_resid": st["true_resid"], "S": S,
+                     "hop_launches": q["count"], "hop_ms_per_launch": q["ms"] / max(q["count"], 1),
+                     "ms_per_iteration": 1e3 * sec / max(1, sum(st["iters"]))}
+        log(f"dense: {name}: {sec:.2f} s, iters {st['iters']}, resid {st['true_resid']}")
+    d = sols["dense_fp64"]
+    for name in res:
+        a = sols[name]
+        res[name]["chi_rel_diff_vs_dense"] = max(
+            float(torch.linalg.vector_norm(a[i] - d[i]) / torch.linalg.vector_norm(d[i])) for i in range(2))
+    ctx.close()
+    out = {"metric": "EOFA solve: dense D_EOFA vs Cayley form (Table 4 columns), seconds to 1e-10, 1 GPU",
+           "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
+                                  f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}: both systems"},
+           "data": "synthetic (random SU(3) links exp(i eps H), Gaussian phi)",
+           "solves": res,
+           "cayley_fp64_speedup": res["dense_fp64"]["seconds"] / res["cayley_fp64"]["seconds"],
+           f"cayley_{args.inner}_speedup": res["dense_fp64"]["seconds"] / res[f"cayley_{args.inner}"]["seconds"]}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def trajectory(args):
     """The 24^3x64, Ls = 24 trajectory workload (c5): a fermion-only EOFA
     leapfrog trajectory of n_steps x dt from seeded links, pseudofermion and
@@ -275,11 +333,11 @@ def trajectory(args):
         U, P = U0.clone(), P0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
+        H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
         prog = lambda i, st, lab=label: log(f"trajectory {lab}: force {i}: iters {st['iters']} "
                                             f"solve {st['seconds']:.2f}s")
         leapfrog(ctx, U, P, phi, m1, m2, n, dt, progress=prog, **solver)
-        H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
+        H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         log(f"trajectory {label}: H0 {H0:.6f} H1 {H1:.6f} dH {H1 - H0:.6e} ({sec:.1f} s)")
@@ -449,7 +507,7 @@ def hmc(args):
     t_hb = time.perf_counter() - t0
     log(f"hmc: interval [{lo:.4f}, {hi:.3f}] ({t_int:.1f} s), heatbath {n_poles} poles {t_hb:.1f} s")
     t0 = time.perf_counter()
-    H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+    H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
     sync()
     t_h0 = time.perf_counter() - t0
     prog = lambda i, st: log(f"hmc: force {i}: iters {st['iters']} solve {st['seconds']:.2f}s")
@@ -460,7 +518,7 @@ def hmc(args):
     sync()
     t_md = time.perf_counter() - t0
     t0 = time.perf_counter()
-    H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, **solver)
+    H1, S1, K1, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
     sync()
     t_h1 = time.perf_counter() - t0
     ee = float(np.vdot(eta_h, eta_h).real)
@@ -523,6 +581,8 @@ def main():
                     help="hmc: inner force-gradient steps of the gauge dynamics per link update")
     ap.add_argument("--chrono", type=int, default=8,
                     help="hmc: earlier solutions per system for chronological guesses in the MD (0: none)")
+    ap.add_argument("--dense", action="store_true",
+                    help="solve on D_EOFA itself (dense 5D blocks) against the Cayley form")
     ap.add_argument("--gauge", action="store_true",
                     help="time the Iwasaki and Wilson gauge force and action kernels")
     ap.add_argument("--dslash", action="store_true",
@@ -545,6 +605,8 @@ def main():
         return dslash(args)
     if args.gauge:
         return gauge(args)
+    if args.dense:
+        return dense(args)
 
     import torch
     import dwf_inputs as din

@@ -118,6 +118,20 @@ int eofa_solve(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
                const void *x0_L_dev, const void *x0_R_dev, void *chiL_dev, void *chiR_dev,
                void *Mphi_dev, double *S_out, const eofa_solver_t *solver, eofa_stats_t *stats);
 
+/* The same EOFA solves without the Cayley-form right preconditioning: the
+ * comparison path of Table 4 ("EOFA (dense)").  Each system is solved as
+ * D_EOFA chi = gamma_5 R_5 v with D_EOFA = D_w + (1 - L) Dtilde^-1, whose
+ * 5D structure is dense: even-odd CGNR on
+ *   Mhat = D5 - Dh_oe D5^-1 Dh_eo,  D5 = (4 - M5) + (1 - L) Dtilde^-1,
+ * D5 applied as one Ls x Ls block per chirality.  The residual
+ * b - D_EOFA chi equals the Cayley form's b - D_DWF y (chi = Dtilde y), so
+ * `solver->tol` means the same in both.  FP64 only (solver->inner must be
+ * EOFA_FP64); no initial guesses.  Arguments, outputs and errors as in
+ * eofa_solve; stats->reliable_updates are 0. */
+int eofa_solve_dense(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev, void *chiL_dev,
+                     void *chiR_dev, void *Mphi_dev, double *S_out, const eofa_solver_t *solver,
+                     eofa_stats_t *stats);
+
 /* Rational approximation for the heatbath of Section 3.2: the best
  * relative-error approximation of x^(-1/2) on [lo, hi] of type (n, n),
  *   x^(-1/2) ~ alpha0 + sum_{l<n} alpha[l] / (beta[l] + x),
@@ -237,7 +251,7 @@ int eofa_gauge_force(eofa_ctx_t *ctx, const void *U_dev, double beta, double c1,
  * eofa_timing_query synchronises and returns, for kernel class `name`
  * ("hop" = the 5D hopping kernel in any precision, "hop64", "hop32",
  * "hop16", "hopb16", "blas", "force", "md", "gauge_force",
- * "gauge_action"), the launch count, the summed
+ * "gauge_action", "hop64_dense"), the launch count, the summed
  * duration in ms and the summed algorithmic bytes. */
 int eofa_timing_enable(eofa_ctx_t *ctx, int on);
 int eofa_timing_query(eofa_ctx_t *ctx, const char *name, long *count, double *ms, double *bytes);

@@ -15,7 +15,7 @@ EOFA_OK, EOFA_EINVAL, EOFA_ENOMEM, EOFA_ENOCONV, EOFA_ENAN, EOFA_EDEVICE = 0, -1
 PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 
 EXPORTS = [
-    "eofa_ctx_create", "eofa_ctx_destroy", "eofa_ctx_update_gauge", "dwf_apply", "eofa_solve",
+    "eofa_ctx_create", "eofa_ctx_destroy", "eofa_ctx_update_gauge", "dwf_apply", "eofa_solve", "eofa_solve_dense",
     "eofa_force", "eofa_md_update", "eofa_rational_inv_sqrt", "eofa_heatbath", "eofa_meofa_bounds", "eofa_chrono",
     "eofa_gauge_action", "eofa_gauge_force", "eofa_timing_enable",
     "eofa_timing_query", "eofa_last_error",
@@ -65,6 +65,8 @@ def load() -> C.CDLL:
         "dwf_apply": (I_, [P, D, D, I_, I_, I_, P, P]),
         "eofa_solve": (I_, [P, D, D, P, P, P, P, P, P, C.POINTER(C.c_double), C.POINTER(Solver),
                             C.POINTER(Stats)]),
+        "eofa_solve_dense": (I_, [P, D, D, P, P, P, P, C.POINTER(C.c_double), C.POINTER(Solver),
+                                  C.POINTER(Stats)]),
         "eofa_force": (I_, [P, D, D, P, P, P, P, P, C.POINTER(Solver), C.POINTER(Stats)]),
         "eofa_md_update": (I_, [P, P, P, P, D, D, C.POINTER(C.c_double)]),
         "eofa_rational_inv_sqrt": (I_, [D, D, I_, C.POINTER(C.c_double), C.POINTER(C.c_double),

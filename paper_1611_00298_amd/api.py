@@ -132,6 +132,23 @@ class Context:
         d["converged"] = rc == _lib.EOFA_OK
         return chiL, chiR, Mphi, S.value, d
 
+    def eofa_solve_dense(self, phi, m1, m2, tol=1e-10, maxiter=20000, want_mphi=True, allow_noconv=False):
+        """The same solves on D_EOFA itself, without the Cayley form (the
+        FP64 comparison path).  Returns (chi_L, chi_R, M_EOFA phi or None, S, stats)."""
+        _want(phi, self.shape_phi, "phi")
+        chiL = torch.empty(self.shape5, dtype=torch.complex128, device=self.device)
+        chiR = torch.empty_like(chiL)
+        Mphi = torch.empty_like(phi) if want_mphi else None
+        S = C.c_double(0.0)
+        sp = make_solver(tol, maxiter, "fp64", 0.0)
+        st = Stats()
+        rc = self.lib.eofa_solve_dense(self.handle, float(m1), float(m2), _ptr(phi), _ptr(chiL), _ptr(chiR),
+                                       _ptr(Mphi), C.byref(S), C.byref(sp), C.byref(st))
+        check(rc, allow_noconv)
+        d = st.as_dict()
+        d["converged"] = rc == _lib.EOFA_OK
+        return chiL, chiR, Mphi, S.value, d
+
     # -- eofa_heatbath ---------------------------------------------------------
     def eofa_heatbath(self, eta, m1, m2, coeffs=None, lo=None, hi=None, n_poles=None, tol=1e-10,
                       maxiter=20000, inner="fp64", reliable_delta=0.3, forecast=8, allow_noconv=False):
@@ -265,6 +282,10 @@ def dwf_apply(ctx: Context, psi, m_plus, m_minus, dagger=False, eo=False, prec="
 
 def eofa_solve(ctx: Context, phi, m1, m2, **kw):
     return ctx.eofa_solve(phi, m1, m2, **kw)
+
+
+def eofa_solve_dense(ctx: Context, phi, m1, m2, **kw):
+    return ctx.eofa_solve_dense(phi, m1, m2, **kw)
 
 
 def eofa_heatbath(ctx: Context, eta, m1, m2, **kw):

@@ -77,6 +77,7 @@ hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, con
 int md_blocks(int nlink);
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st);
+hipError_t launch_hop_dense(bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
 int gauge_action_blocks(int V);
 hipError_t launch_gauge_force(const void* U, void* F, const int L[4], double beta, double c1, int accumulate,
                               hipStream_t st);
@@ -112,9 +113,10 @@ struct Half {
     int prec = -1;
 };
 
-enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_MD, C_GFORCE, C_GACTION, C_NCLS };
+enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_MD, C_GFORCE, C_GACTION, C_HOPDENSE,
+           C_NCLS };
 const char* cls_name[C_NCLS] = {"hop64", "hop32", "hop16", "hopb16", "blas", "force", "md",
-                                "gauge_force", "gauge_action"};
+                                "gauge_force", "gauge_action", "hop64_dense"};
 
 struct TimingRec {
     int cls;
@@ -243,7 +245,13 @@ Op5 DtInv(const eofa_ctx* c, int tr) { return Op5{2, tr, c->b5, c->c5}; }
 Op5 Mee(const eofa_ctx* c, int tr) { return Op5{1, tr, c->beta0, c->beta1}; }
 Op5 MeeInv(const eofa_ctx* c, int tr) { return Op5{2, tr, c->beta0, c->beta1}; }
 
-double op_flops(const Op5& o) { return o.kind == 1 ? 72.0 : o.kind == 2 ? 144.0 : 0.0; }
+// flops per 5D site: bidiagonal 72, inverse 144, dense block 48 Ls (24 reals x Ls multiply-adds)
+double op_flops(const Op5& o, int Ls) {
+    return o.kind == 1 ? 72.0 : o.kind == 2 ? 144.0 : o.kind == 3 ? 48.0 * Ls : 0.0;
+}
+// the dense blocks of D_EOFA's even-odd form (uploaded per mass pair by solve_dense)
+Op5 D5(int tr) { return Op5{3, tr, 0.0, 0.0}; }
+Op5 D5Inv(int tr) { return Op5{3, tr, 1.0, 0.0}; }
 
 struct HopCall {
     int prec = P64;
@@ -261,6 +269,8 @@ struct HopCall {
     // ch and ca scaled on the device by sc[s_num] / sc[s_den] (saved to sc[s_alpha])
     bool dev_alpha = false;
     int s_num = 0, s_den = 0, s_alpha = -1;
+    // dense blocks [D5+, D5-, D5inv+, D5inv-] (FP64 dense comparison path only)
+    const double* dmat = nullptr;
 };
 
 void run_hop(eofa_ctx* c, const HopCall& h) {
@@ -320,10 +330,10 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     }
     // bookkeeping: flops (fixed convention) and algorithmic bytes
     double f = 0, nfields = 1;
-    if (h.hop) f += 1320.0 + op_flops(h.A), nfields += 1;
-    if (h.aux) f += op_flops(h.B) + op_flops(h.B2) + (h.hop ? 24.0 : 0.0), nfields += 1;
+    if (h.hop) f += 1320.0 + op_flops(h.A, c->Ls), nfields += 1;
+    if (h.aux) f += op_flops(h.B, c->Ls) + op_flops(h.B2, c->Ls) + (h.hop ? 24.0 : 0.0), nfields += 1;
     if (h.aux2) f += 24.0, nfields += 1;
-    f += op_flops(h.C);
+    f += op_flops(h.C, c->Ls);
     c->flops += f * (double)c->n5;
     double bytes = nfields * spinor_bytes(h.prec) * (double)c->n5;
     // algorithmic link bytes: the 4V links of one checkerboard hop, 9 complex
@@ -331,6 +341,15 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     // FP32 links or the FP16 rows of the matrix-core path)
     if (h.hop) bytes += 72.0 * complex_bytes(h.prec) * c->Vh;
     const int ev = timing_begin(c);
+    if (h.dmat) {
+        if (h.prec != P64 || h.C.kind != 0 || h.B2.kind != 0 || h.dev_alpha)
+            fail(EOFA_EDEVICE, "internal: unsupported dense hop form");
+        a.dmat = h.dmat;
+        hipchk(launch_hop_dense(h.dag, h.hop, a, c->nblk_hop, c->st), "dense hop kernel");
+        timing_end(c, ev, h.hop ? C_HOPDENSE : C_BLAS, bytes);
+        return;
+    }
+    if (h.A.kind == 3 || h.B.kind == 3) fail(EOFA_EDEVICE, "internal: dense block without matrices");
     hipchk(launch_hop(h.prec, h.dag, h.hop, a, c->nblk_hop, c->st), "hop kernel");
     timing_end(c, ev, h.hop ? (int)h.prec : C_BLAS, bytes);
 }
@@ -808,6 +827,228 @@ CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const 
         have = true;
     }
     return out;
+}
+
+void validate_solver(const eofa_solver_t* sp);
+void omega_k(const eofa_ctx* c, double m1, double m2, double* k);
+
+// ---- the dense D_EOFA comparison path (Table 4, "EOFA (dense)") --------------
+// D_EOFA = D_DWF Dtilde^-1 = D_w + (1 - L) Dtilde^-1: the Wilson hop, diagonal
+// in s, plus the site-local D5 = (4 - M5) + (1 - L) Dtilde^-1, dense in s (one
+// Ls x Ls block per chirality).  Without the Cayley-form right
+// preconditioning the EOFA systems D_EOFA chi = b are solved as they stand:
+// even-odd, Mhat = D5 - Dh_oe D5^-1 Dh_eo on odd sites, FP64 CGNR.  Since
+// D_DWF = D_EOFA Dtilde, b - D_EOFA chi is exactly the residual b - D_DWF y of
+// the Cayley-form solve (chi = Dtilde y), so the two paths stop on the same
+// quantity.
+
+// in-place inverse of a row-major n x n matrix, Gauss-Jordan with partial pivoting
+void invert_dense(int n, std::vector<double>& A) {
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
+        const double d = A[(size_t)piv * n + col];
+        if (!(std::fabs(d) > 0.0) || !std::isfinite(d)) fail(EOFA_EINVAL, "singular 5D block of D_EOFA");
+        if (piv != col)
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[(size_t)piv * n + k], A[(size_t)col * n + k]);
+                std::swap(I[(size_t)piv * n + k], I[(size_t)col * n + k]);
+            }
+        for (int k = 0; k < n; ++k) {
+            A[(size_t)col * n + k] /= d;
+            I[(size_t)col * n + k] /= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            const double f = A[(size_t)r * n + col];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[(size_t)r * n + k] -= f * A[(size_t)col * n + k];
+                I[(size_t)r * n + k] -= f * I[(size_t)col * n + k];
+            }
+        }
+    }
+    A.swap(I);
+}
+
+// [D5+, D5-, D5inv+, D5inv-] for boundary masses (m+, m-), each Ls x Ls row
+// major, with L+ (m+) acting on spins 0, 1 and L- (m-) on spins 2, 3
+std::vector<double> dense_blocks(const eofa_ctx* c, double mp, double mm) {
+    const int n = c->Ls;
+    const size_t nn = (size_t)n * n;
+    std::vector<double> out(4 * nn);
+    for (int ch = 0; ch < 2; ++ch) {
+        const double m = ch == 0 ? mp : mm;
+        std::vector<double> L(nn, 0.0);
+        for (int s = 0; s < n; ++s) {
+            if (ch == 0) {   // (L+ v)_s = v_{s-1}, (L+ v)_0 = -m+ v_{Ls-1}
+                if (s >= 1) L[(size_t)s * n + s - 1] += 1.0;
+                else L[(size_t)n - 1] += -m;
+            } else {         // (L- v)_s = v_{s+1}, (L- v)_{Ls-1} = -m- v_0
+                if (s <= n - 2) L[(size_t)s * n + s + 1] += 1.0;
+                else L[(size_t)(n - 1) * n] += -m;
+            }
+        }
+        std::vector<double> Dti(nn);
+        for (size_t q = 0; q < nn; ++q) Dti[q] = c->c5 * L[q];
+        for (int i = 0; i < n; ++i) Dti[(size_t)i * n + i] += c->b5;
+        invert_dense(n, Dti);
+        std::vector<double> D((nn));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double v = Dti[(size_t)i * n + j] + (i == j ? 4.0 - c->M5 : 0.0);
+                for (int k = 0; k < n; ++k) v -= L[(size_t)i * n + k] * Dti[(size_t)k * n + j];
+                D[(size_t)i * n + j] = v;
+            }
+        std::copy(D.begin(), D.end(), out.begin() + ch * nn);
+        invert_dense(n, D);
+        std::copy(D.begin(), D.end(), out.begin() + (2 + ch) * nn);
+    }
+    return out;
+}
+
+struct DenseOut {
+    int iters = 0;
+    double true_resid = 0;
+    bool converged = false;
+};
+
+// Dense hop forms: out = ch DA(Dh in) + ca DB(aux) + cr aux2 on output parity par
+void dense_hop(eofa_ctx* c, const double* dm, bool dag, int par, const Half* in, Half& out, Op5 A, double ch,
+               const Half* aux, Op5 B, double ca, const Half* aux2, double cr, double* partial) {
+    HopCall h;
+    h.prec = P64; h.dag = dag; h.hop = in != nullptr; h.par = par; h.in = in; h.out = &out;
+    h.A = A; h.ch = ch; h.aux = aux; h.B = B; h.ca = ca; h.aux2 = aux2; h.cr = cr;
+    h.partial = partial; h.dmat = dm;
+    run_hop(c, h);
+}
+
+DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& bo, Half& xe, Half& xo,
+                     const eofa_solver_t& sp) {
+    DenseOut out;
+    const int nb = c->nblk_hop;
+    const double b2 = norm2(c, be, S_B2) + norm2(c, bo, S_B2);
+    check_finite(b2, "source norm");
+    if (b2 == 0.0) {
+        zero(c, xe); zero(c, xo);
+        out.converged = true;
+        return out;
+    }
+    const double bnorm = std::sqrt(b2);
+    Half& t = ws(c, "dn_t", P64);
+    Half& bh = ws(c, "dn_bhat", P64);
+    Half& sr = ws(c, "dn_s", P64);   // s = bhat - Mhat x_o
+    Half& r = ws(c, "dn_r", P64);    // r = Mhat^dag s
+    Half& p = ws(c, "dn_p", P64);
+    Half& w = ws(c, "dn_w", P64);
+    // bhat_o = b_o - Dh_oe D5^-1 b_e
+    dense_hop(c, dm, false, 0, nullptr, t, I5, 1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
+    dense_hop(c, dm, false, 1, &t, bh, I5, -1.0, nullptr, I5, 0.0, &bo, 1.0, nullptr);
+    zero(c, xo);
+    convert(c, bh, sr);
+    auto mhat = [&](const Half& in, Half& o, double* partial) {   // o = Mhat in
+        dense_hop(c, dm, false, 0, &in, t, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+        dense_hop(c, dm, false, 1, &t, o, I5, -1.0, &in, D5(0), 1.0, nullptr, 0.0, partial);
+    };
+    auto mhat_dag = [&](const Half& in, Half& o, double* partial) {   // o = Mhat^dag in
+        dense_hop(c, dm, true, 0, &in, t, D5Inv(1), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+        dense_hop(c, dm, true, 1, &t, o, I5, -1.0, &in, D5(1), 1.0, nullptr, 0.0, partial);
+    };
+    mhat_dag(sr, r, c->partial);
+    reduce(c, nb, S_T0);
+    double gam = read_slot(c, S_T0);
+    check_finite(gam, "dense CG");
+    convert(c, r, p);
+    const double target = sp.tol * bnorm;
+    while (out.iters < sp.maxiter && gam > 0.0) {
+        mhat(p, w, c->partial);
+        reduce(c, nb, S_T0);
+        const double ww = read_slot(c, S_T0);
+        check_finite(ww, "dense CG");
+        if (!(ww > 0.0)) break;
+        const double alpha = gam / ww;
+        hipchk(launch_caxpy64(xo.d, p.d, alpha, 0.0, c->n5, c->N, c->nblk_blas, c->st), "caxpy");
+        hipchk(launch_caxpy64(sr.d, w.d, -alpha, 0.0, c->n5, c->N, c->nblk_blas, c->st), "caxpy");
+        ++out.iters;
+        const double ss = norm2(c, sr, S_T1);
+        check_finite(ss, "dense CG");
+        if (std::sqrt(ss) <= target) break;
+        mhat_dag(sr, r, c->partial);
+        reduce(c, nb, S_T0);
+        const double g2 = read_slot(c, S_T0);
+        check_finite(g2, "dense CG");
+        // p <- r + (g2 / gam) p
+        dense_hop(c, dm, false, 0, nullptr, p, I5, 1.0, &p, I5, g2 / gam, &r, 1.0, nullptr);
+        gam = g2;
+    }
+    // x_e = D5^-1 (b_e - Dh_eo x_o)
+    dense_hop(c, dm, false, 0, &xo, xe, D5Inv(0), -1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
+    // true residual of the full system: b_p - D5 x_p - Dh x_pbar
+    Half& rt = ws(c, "rt", P64);
+    for (int par = 0; par < 2; ++par)
+        dense_hop(c, dm, false, par, par ? &xe : &xo, rt, I5, -1.0, par ? &xo : &xe, D5(0), -1.0,
+                  par ? &bo : &be, 1.0, c->partial + (size_t)par * nb);
+    reduce(c, 2 * nb, S_T0);
+    const double rr = read_slot(c, S_T0);
+    check_finite(rr, "true residual");
+    out.true_resid = std::sqrt(rr) / bnorm;
+    out.converged = out.true_resid <= sp.tol;
+    return out;
+}
+
+int solve_dense_impl(eofa_ctx* c, double m1, double m2, const void* phi, void* chiL, void* chiR, void* Mphi,
+                     double* S, const eofa_solver_t* sp, eofa_stats_t* stats) {
+    if (!c || !phi || !chiL || !chiR) fail(EOFA_EINVAL, "NULL argument");
+    validate_solver(sp);
+    if (sp->inner != EOFA_FP64) fail(EOFA_EINVAL, "the dense D_EOFA path runs in FP64 only");
+    if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
+    double k;
+    omega_k(c, m1, m2, &k);
+    const auto t0 = std::chrono::steady_clock::now();
+    const double f0 = c->flops;
+    Half& bLe = ws(c, "bL_e", P64);
+    Half& bLo = ws(c, "bL_o", P64);
+    Half& bRe = ws(c, "bR_e", P64);
+    Half& bRo = ws(c, "bR_o", P64);
+    hipchk(launch_eofa_source(phi, c->om, bLe.d, bLo.d, bRe.d, bRo.d, c->L, c->Ls, c->N, c->st), "source");
+    Half& ce = ws(c, "chi_e", P64);
+    Half& co = ws(c, "chi_o", P64);
+    const size_t nmat = (size_t)4 * c->Ls * c->Ls;
+    int status = EOFA_OK;
+    for (int sys = 0; sys < 2; ++sys) {
+        const double mp = m1, mm = sys == 0 ? m1 : m2;
+        const std::vector<double> blocks = dense_blocks(c, mp, mm);
+        double* dm = (double*)rawbuf(c, sys ? "dense_R" : "dense_L", nmat * sizeof(double));
+        hipchk(hipMemcpyAsync(dm, blocks.data(), nmat * sizeof(double), hipMemcpyHostToDevice, c->st),
+               "hipMemcpy(dense blocks)");
+        hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+        const DenseOut o = solve_dense(c, dm, sys ? bRe : bLe, sys ? bRo : bLo, ce, co, *sp);
+        hipchk(launch_dev_to_nat5(sys ? chiR : chiL, ce.d, co.d, c->L, c->Ls, c->N, c->st), "layout");
+        if (stats) {
+            stats->iters[sys] = o.iters;
+            stats->reliable_updates[sys] = 0;
+            stats->true_resid[sys] = o.true_resid;
+        }
+        if (!o.converged) status = EOFA_ENOCONV;
+    }
+    if (S || Mphi) {
+        const int nb = action_blocks(c->V);
+        hipchk(launch_eofa_action(phi, chiL, chiR, c->om, k, Mphi, c->partial, c->V, c->Ls, c->st), "action");
+        reduce(c, nb, S_T1);
+        const double s = read_slot(c, S_T1);
+        check_finite(s, "action");
+        if (S) *S = s;
+    }
+    hipchk(hipStreamSynchronize(c->st), "hipStreamSynchronize");
+    if (stats) {
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->flops = c->flops - f0;
+    }
+    if (status != EOFA_OK) g_err = "solver did not reach the requested true residual";
+    return status;
 }
 
 void validate_solver(const eofa_solver_t* sp) {
@@ -1522,6 +1763,11 @@ int eofa_md_update(eofa_ctx_t* c, void* U, void* P, const void* F, double dt_p, 
         }
         return EOFA_OK;
     });
+}
+
+int eofa_solve_dense(eofa_ctx_t* c, double m1, double m2, const void* phi, void* chiL, void* chiR, void* Mphi,
+                     double* S, const eofa_solver_t* sp, eofa_stats_t* stats) {
+    return guarded([&]() -> int { return solve_dense_impl(c, m1, m2, phi, chiL, chiR, Mphi, S, sp, stats); });
 }
 
 int eofa_gauge_action(eofa_ctx_t* c, const void* U, double beta, double c1, double* S) {

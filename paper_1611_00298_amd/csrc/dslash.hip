@@ -538,6 +538,34 @@ __device__ __forceinline__ void row_bidiag(const A* T, int tid, int s, int Ls, c
     for (int k = 12; k < 24; ++k) out[k] = fmadd(fl, rl[k], a * x[k]);
 }
 
+// Dense 5D block (kind-3 Op5): v_s <- scale sum_t M[s][t] v_t, with M the
+// P+ block for spins 0, 1 and the P- block for spins 2, 3.  The rows of the
+// workgroup are staged in T; every work-item takes part (two barriers).
+template <typename A>
+__device__ void row_dense(A* T, int tid, int sl, int s, int Ls, A (&v)[24], const double* __restrict__ dm,
+                          const Op5& op, A scale) {
+    put_row(T, tid, v);
+    __syncthreads();
+    const double* Mu = dm + (size_t)(op.a != 0.0 ? 2 : 0) * Ls * Ls;
+    const double* Ml = Mu + (size_t)Ls * Ls;
+    const int rs = op.tr ? 1 : Ls, cs = op.tr ? Ls : 1;   // M[s][t] at s rs + t cs
+    const A* base = T + sl * Ls * STR;
+    A acc[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] = 0;
+    for (int t = 0; t < Ls; ++t) {
+        const A mu = (A)Mu[s * rs + t * cs], ml = (A)Ml[s * rs + t * cs];
+        const A* r = base + t * STR;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = fmadd(mu, r[k], acc[k]);
+#pragma unroll
+        for (int k = 12; k < 24; ++k) acc[k] = fmadd(ml, r[k], acc[k]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = scale * acc[k];
+}
+
 template <typename A>
 __device__ __forceinline__ A ipow(A x, int e) {
     A r = 1;
@@ -637,7 +665,7 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
     return t;
 }
 
-template <int P, bool DAG, bool HOP, int MF>
+template <int P, bool DAG, bool HOP, int MF, bool DENSE = false>
 __global__ void __launch_bounds__(256, (MF == 3 && P == P16) ? 5 : 3) k_hop(const HopArgs a) {
     using A = typename PT<P>::A;
     // column-sweep load batch: what each variant's register budget allows
@@ -676,6 +704,38 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16) ? 5 : 3) k_hop(cons
         }
         __syncthreads();   // the epilogue reuses the staged LDS area
     }
+    if constexpr (DENSE) {
+        // D_EOFA's even-odd form: out = ch DA(hop) + ca DB(aux) + cr aux2
+        // (local: out = ca DB(aux) + cr aux2), DA and DB dense or identity
+        if (HOP) {
+            if (a.opA.kind == 3) row_dense(lds, tid, sl, s, Ls, v, a.dmat, a.opA, (A)a.ch);
+            else {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] *= (A)a.ch;
+            }
+        }
+        if (a.aux) {
+            A x[24];
+            if (active) ld_spinor<P, true>(a.aux, a.aux_nrm, a.N, n, x);
+            else {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) x[k] = 0;
+            }
+            if (a.opB.kind == 3) row_dense(lds, tid, sl, s, Ls, x, a.dmat, a.opB, (A)a.ca);
+            else {
+#pragma unroll
+                for (int k = 0; k < 24; ++k) x[k] *= (A)a.ca;
+            }
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] += x[k];
+        }
+        if (a.aux2 && active) {
+            A x[24];
+            ld_spinor<P, true>(a.aux2, a.aux2_nrm, a.N, n, x);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] = fmadd((A)a.cr, x[k], v[k]);
+        }
+    } else {
     double alpha = 1.0;
     if (a.dsc) {
         alpha = a.dsc[a.s_num] / a.dsc[a.s_den];
@@ -753,6 +813,7 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16) ? 5 : 3) k_hop(cons
             for (int k = 0; k < 24; ++k) v[k] = fmadd(cr, x[k], v[k]);
         }
     }
+    }   // !DENSE
     if (active) st_spinor<P, true>(a.out, a.out_nrm, a.N, n, v);
     if (a.partial) {
         double x = 0;
@@ -853,6 +914,22 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     const size_t shm = HOP ? std::max(tile, stage_bytes(LinkLds<P, 0>::LB, a.NS)) : tile;
     hipLaunchKernelGGL((k_hop<P, DAG, HOP, 0>), dim3(nblk), dim3(NT), shm, st, a);
     return hipGetLastError();
+}
+
+// FP64 hop with dense 5D blocks (kind-3 Op5s), for D_EOFA's even-odd form
+template <bool DAG, bool HOP>
+static hipError_t launch_hop_dense_t(const HopArgs& a, int nblk, hipStream_t st) {
+    const int NT = a.NS * a.Ls;
+    const size_t tile = (size_t)STR * NT * sizeof(double);
+    const size_t shm = HOP ? std::max(tile, stage_bytes(LinkLds<P64, 0>::LB, a.NS)) : tile;
+    hipLaunchKernelGGL((k_hop<P64, DAG, HOP, 0, true>), dim3(nblk), dim3(NT), shm, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hop_dense(bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st) {
+    if (!a.dmat) return hipErrorInvalidValue;
+    if (hop) return dag ? launch_hop_dense_t<true, true>(a, nblk, st) : launch_hop_dense_t<false, true>(a, nblk, st);
+    return launch_hop_dense_t<false, false>(a, nblk, st);
 }
 
 hipError_t launch_hop(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st) {

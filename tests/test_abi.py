@@ -69,6 +69,8 @@ def test_null_arguments_are_rejected():
     assert lib.eofa_meofa_bounds(None, 0.1, 0.2, None, 10, C.byref(sp), None, None,
                                  None) == _lib.EOFA_EINVAL
     assert lib.eofa_chrono(None, 4) == _lib.EOFA_EINVAL
+    assert lib.eofa_solve_dense(None, 0.1, 0.2, None, None, None, None, None, C.byref(sp),
+                                None) == _lib.EOFA_EINVAL
     S = C.c_double(0.0)
     assert lib.eofa_gauge_action(None, None, 2.0, -0.331, C.byref(S)) == _lib.EOFA_EINVAL
     assert lib.eofa_gauge_force(None, None, 2.0, -0.331, None, 0) == _lib.EOFA_EINVAL
