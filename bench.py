@@ -282,6 +282,8 @@ def dense(args):
         sols[name] = (chiL, chiR)
         res[name] = {"seconds": sec, "iters": st["iters"], "true_resid": st["true_resid"], "S": S,
                      "hop_launches": q["count"], "hop_ms_per_launch": q["ms"] / max(q["count"], 1),
+                     "hop_GBs": q["bytes"] / max(q["ms"], 1e-9) / 1e6,
+                     "hop_frac": q["bytes"] / max(q["ms"], 1e-9) / 1e6 / HBM_PEAK_GBS,
                      "ms_per_iteration": 1e3 * sec / max(1, sum(st["iters"]))}
         log(f"dense: {name}: {sec:.2f} s, iters {st['iters']}, resid {st['true_resid']}")
     d = sols["dense_fp64"]
