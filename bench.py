@@ -58,6 +58,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def plaquette(ctx, U):
+    """Average plaquette Re tr U_P / 3 of the links U, from the Wilson gauge
+    action on the GPU: S_W = beta sum_x sum_{mu<nu} (1 - Re tr U_P / 3)."""
+    L = ctx.L
+    return 1.0 - ctx.gauge_action(U, 1.0, 0.0) / (6.0 * L[0] * L[1] * L[2] * L[3])
+
+
 def measured_traffic(inner, workload):
     """HBM bytes per launch of the hopping kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None if
@@ -195,6 +202,61 @@ GAUGE_ACTION_FLOPS = {"iwasaki": 6 * (2 * 198 + 36) + 12 * (4 * 198 + 36), "wils
 FP64_PEAK_TFLOPS = 78.6
 
 
+def gauge_cpu_baseline():
+    """The oracle's Iwasaki gauge force and action (numpy, loops as step
+    lists) on a 24^3x4 slab of the workload's links, beside the GPU kernels
+    on the same slab."""
+    import numpy as np
+    import torch
+    import dwf_inputs as din
+    import oracle
+    from paper_1611_00298_amd import IWASAKI_C1, Context
+    L = (24, 24, 24, 4)
+    U = din.random_gauge(L, 0.5, 103)
+    t0 = time.perf_counter()
+    F = oracle.gauge_force(U, 2.13, IWASAKI_C1)
+    t_force = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    S = oracle.gauge_action(U, 2.13, IWASAKI_C1)
+    t_action = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    Ud = torch.from_numpy(U).to(dev)
+    with Context(L, 2, Ud) as ctx:
+        Fg = ctx.gauge_force(Ud, 2.13, IWASAKI_C1).cpu().numpy()
+        Sg = ctx.gauge_action(Ud, 2.13, IWASAKI_C1)
+    nl = 4 * L[0] * L[1] * L[2] * L[3]
+    return {"value": nl / t_force, "unit": "links/s (force)", "cores": 1, "kind": "oracle",
+            "sample": "Iwasaki force and action on a 24^3x4 slab (numpy, FP64)",
+            "force_s": t_force, "action_s": t_action,
+            "gpu_vs_oracle": {"F_maxabs_rel": float(np.abs(Fg - F).max() / np.abs(F).max()),
+                              "S_rel": abs(Sg - S) / abs(S)}}
+
+
+def dense_cpu_baseline():
+    """The oracle's direct-path operator H = gamma_5 R_5 D_EOFA (FP64, OpenMP),
+    which its non-Cayley solve iterates, applied to a 24^3x4, Ls = 24 slab."""
+    import numpy as np
+    import dwf_inputs as din
+    import oracle
+    pre = din.preset("c3")
+    L = (24, 24, 24, 4)
+    lat = oracle.Lattice(L, pre["Ls"], M5=pre["M5"], alpha=pre["alpha"])
+    U = din.random_gauge(L, pre["eps"], 103)
+    psi = din.gaussian_5d(L, pre["Ls"], 303)
+    oracle.H_op(lat, U, pre["m1"], pre["m2"], psi)   # warm-up
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < 10.0:
+        psi = oracle.H_op(lat, U, pre["m1"], pre["m2"], psi)
+        psi /= np.linalg.norm(psi)
+        n += 1
+    t = (time.perf_counter() - t0) / n
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    scale = 64 / 4
+    return {"value": 1e3 * t * scale, "unit": "ms per full-lattice H application (slab time x 16)",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{n} applications of H = g5 R5 D_EOFA on a 24^3x4, Ls=24 slab (FP64, OpenMP)"}
+
+
 def gauge(args):
     """The gauge action of Table 1's ensembles (Iwasaki, c1 = -0.331; Wilson,
     c1 = 0) and its force on the workload's links: 20 force and 5 action
@@ -240,6 +302,9 @@ def gauge(args):
         ctx.timing_enable(False)
         out["actions"][name] = res
     ctx.close()
+    if not args.no_cpu_baseline:
+        log("gauge: CPU oracle baseline")
+        out["cpu_baseline"] = gauge_cpu_baseline()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -299,6 +364,9 @@ def dense(args):
            "solves": res,
            "cayley_fp64_speedup": res["dense_fp64"]["seconds"] / res["cayley_fp64"]["seconds"],
            f"cayley_{args.inner}_speedup": res["dense_fp64"]["seconds"] / res[f"cayley_{args.inner}"]["seconds"]}
+    if not args.no_cpu_baseline:
+        log("dense: CPU oracle baseline")
+        out["cpu_baseline"] = dense_cpu_baseline()
     print(json.dumps(out), flush=True)
     return 0
 
@@ -495,6 +563,7 @@ def hmc(args):
     ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
     solver = dict(tol=1e-10, inner=args.inner, reliable_delta=args.delta)
     gauge = (args.gauge_beta, IWASAKI_C1) if args.gauge_beta > 0 else None
+    plaq0 = plaquette(ctx, U)
     sync = torch.cuda.synchronize
     sync()
     t0 = time.perf_counter()
@@ -524,6 +593,7 @@ def hmc(args):
     sync()
     t_h1 = time.perf_counter() - t0
     ee = float(np.vdot(eta_h, eta_h).real)
+    plaq1 = plaquette(ctx, U)
     ctx.close()
     total = t_int + t_hb + t_h0 + t_md + t_h1
     dH = H1 - H0
@@ -545,7 +615,7 @@ def hmc(args):
                         "S0_over_eta2_minus_1": S0 / ee - 1.0},
            "md": {"force_evaluations": len(fst), "chrono": args.chrono, "solve_iters_total": [sum(s["iters"][0] for s in fst),
                                                                         sum(s["iters"][1] for s in fst)]},
-           "dH": dH, "H0": H0, "S_gauge": [H0 - S0 - K0, H1 - S1 - K1],
+           "dH": dH, "H0": H0, "S_gauge": [H0 - S0 - K0, H1 - S1 - K1], "plaquette": [plaq0, plaq1],
            "accept_probability": float(min(1.0, np.exp(-dH)))}
     print(json.dumps(out), flush=True)
     return 0
@@ -626,6 +696,7 @@ def main():
     m1, m2, tol = pre["m1"], pre["m2"], 1e-10
     ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
     solver = dict(tol=tol, inner=args.inner, reliable_delta=args.delta)
+    plaq = plaquette(ctx, U)
 
     U0, P0 = U.clone(), P.clone()
 
@@ -702,7 +773,8 @@ def main():
         "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
                                f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}: two "
                                f"Cayley-form even-odd CG solves to 1e-10 + action + force + MD step",
-                   "inner_precision": args.inner, "tol": tol, "parallelism": "none (1 GPU)"},
+                   "inner_precision": args.inner, "tol": tol, "parallelism": "none (1 GPU)",
+                   "plaquette": plaq},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.inner, args.workload),

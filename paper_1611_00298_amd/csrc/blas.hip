@@ -30,11 +30,23 @@ __device__ __forceinline__ void block_store_sum(double x, double* dst) {
     }
 }
 
-// out[slot] = sum of partial[0..n) (one workgroup of 1024)
+// out[slot] = sum of partial[0..n) (one workgroup of 1024).  Thread j sums
+// partial[j], partial[j + 1024], ... in that order; the loads are issued 8 at
+// a time so that one workgroup is not bound by the latency of a chain of
+// dependent loads (a hop leaves one partial per workgroup: 55296 at 24^3x64).
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ partial, int n,
                                                  double* out, int slot) {
     double t = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) t += partial[i];
+    const int step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * step < n; i += 8 * step) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = partial[i + q * step];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t += v[q];
+    }
+    for (; i < n; i += step) t += partial[i];
     block_store_sum(t, out + slot);
 }
 
