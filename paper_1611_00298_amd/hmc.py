@@ -196,3 +196,84 @@ def trajectory(ctx: Context, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_
         ctx.update_gauge(U)
     return {"H0": H0, "dH": dH, "S0": S0, "S1": S1, "Sg0": H0 - S0 - K0, "Sg1": H1 - S1 - K1,
             "accepted": accepted, "heatbath": hb, "forces": st}
+
+
+# ---------------------------------------------------------------------------
+# Markov chain with checkpoint and resume
+# ---------------------------------------------------------------------------
+
+def _ckpt_paths(d):
+    import os
+    return os.path.join(d, "links.npy"), os.path.join(d, "state.json")
+
+
+def save_checkpoint(directory, U, rng, records):
+    """Write the links, the generator's state and the trajectory records to
+    `directory` (each file replaced atomically, the state file last)."""
+    import json
+    import os
+
+    import numpy as np
+    os.makedirs(directory, exist_ok=True)
+    links, state = _ckpt_paths(directory)
+    tmp = links + ".tmp.npy"
+    np.save(tmp, U.detach().cpu().numpy())
+    os.replace(tmp, links)
+    doc = {"n_done": len(records), "rng": rng.bit_generator.state, "records": records}
+    with open(state + ".tmp", "w") as fh:
+        json.dump(doc, fh)
+    os.replace(state + ".tmp", state)
+
+
+def load_checkpoint(directory, U, rng):
+    """Restore a checkpoint written by save_checkpoint into U (in place) and
+    rng; returns the trajectory records, or None if there is none."""
+    import json
+    import os
+
+    import numpy as np
+    import torch
+    links, state = _ckpt_paths(directory)
+    if not os.path.exists(state):
+        return None
+    with open(state) as fh:
+        doc = json.load(fh)
+    arr = np.load(links, allow_pickle=False)
+    if tuple(arr.shape) != tuple(U.shape):
+        raise ValueError(f"checkpoint links have shape {arr.shape}, expected {tuple(U.shape)}")
+    U.copy_(torch.from_numpy(arr).to(U.device))
+    if doc["rng"]["bit_generator"] != type(rng.bit_generator).__name__:
+        raise ValueError("checkpoint was written with another bit generator")
+    rng.bit_generator.state = doc["rng"]
+    records = doc["records"]
+    if len(records) != doc["n_done"]:
+        raise ValueError("inconsistent checkpoint")
+    return records
+
+
+def run_chain(ctx: Context, U, n_traj, draw, rng, m1, m2, n_steps, dt, lo, hi, n_poles, checkpoint=None,
+              **kw):
+    """Run the chain up to n_traj trajectories from links U (updated in
+    place).  draw(rng) -> (eta, P, u) gives each trajectory's heatbath noise,
+    momenta and Metropolis uniform (the caller decides how); rng is a
+    numpy Generator.  Every other argument goes to trajectory().  With
+    checkpoint (a directory) the links, rng's state and the records are
+    saved after every trajectory, and an existing checkpoint is resumed
+    first, so a stopped chain continues exactly as if it had not stopped.
+    Returns one record per trajectory (dH, acceptance, actions, iterations)."""
+    records = []
+    if checkpoint is not None:
+        got = load_checkpoint(checkpoint, U, rng)
+        if got is not None:
+            records = got
+    while len(records) < n_traj:
+        eta, P, u = draw(rng)
+        r = trajectory(ctx, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_accept=u, **kw)
+        records.append({"dH": r["dH"], "accepted": r["accepted"], "S0": r["S0"], "S1": r["S1"],
+                        "Sg0": r["Sg0"], "Sg1": r["Sg1"],
+                        "heatbath_iters": list(r["heatbath"]["iters"]),
+                        "md_iters": [sum(s["iters"][0] for s in r["forces"]),
+                                     sum(s["iters"][1] for s in r["forces"])]})
+        if checkpoint is not None:
+            save_checkpoint(checkpoint, U, rng, records)
+    return records

@@ -294,3 +294,40 @@ def test_trajectory_with_gauge_action(c1):
     # rough synthetic fields: an inner leapfrog (n_gauge = 4) gave dH = -0.126 here
     assert r["accepted"] and abs(r["dH"]) < 0.5, r["dH"]
     ctx.update_gauge(to_dev(U0))
+
+
+def _draw_factory(L):
+    T = din.gell_mann() / 2
+    shape4 = (L[3], L[2], L[1], L[0])
+
+    def draw(rng):
+        s = np.sqrt(0.5)
+        eta = rng.normal(scale=s, size=shape4 + (4, 3)) + 1j * rng.normal(scale=s, size=shape4 + (4, 3))
+        p = rng.standard_normal((4,) + shape4 + (8,))
+        P = np.einsum("...a,aij->...ij", p, T)
+        return to_dev(eta), to_dev(P), float(rng.random())
+    return draw
+
+
+def test_chain_checkpoint_resume(c1, tmp_path):
+    """A chain stopped after 2 trajectories and resumed (new link tensor,
+    new generator) ends bit for bit where the uninterrupted chain does."""
+    from paper_1611_00298_amd.hmc import force_gradient, run_chain
+    lat, U0, phi, ctx = c1
+    draw = _draw_factory(C1["L"])
+    kw = dict(integrator=force_gradient, gauge=GAUGE, n_gauge=2, chrono=4, tol=1e-10, inner="fp16")
+    args = (C1["m1"], C1["m2"], 2, 0.1, 0.5, 5.0, 4)
+    Ua = to_dev(U0)
+    ra = run_chain(ctx, Ua, 3, draw, np.random.Generator(np.random.PCG64(7)), *args,
+                   checkpoint=str(tmp_path / "a"), **kw)
+    Ub = to_dev(U0)
+    rb = run_chain(ctx, Ub, 2, draw, np.random.Generator(np.random.PCG64(7)), *args,
+                   checkpoint=str(tmp_path / "b"), **kw)
+    assert rb == ra[:2]
+    Uc = to_dev(np.zeros_like(U0))
+    rc = run_chain(ctx, Uc, 3, draw, np.random.Generator(np.random.PCG64(12345)), *args,
+                   checkpoint=str(tmp_path / "b"), **kw)
+    assert rc == ra
+    assert np.array_equal(Uc.cpu().numpy(), Ua.cpu().numpy())
+    assert len(ra) == 3 and all(abs(r["dH"]) < 1.0 for r in ra)
+    ctx.update_gauge(to_dev(U0))
