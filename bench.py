@@ -788,7 +788,7 @@ def main():
         "other_kernels": other,
         "solve": {"mixed_s": sum(solve_s) / len(solve_s), "iters": recs[-1]["iters"],
                   "reliable_updates": recs[-1]["reliable_updates"],
-                  "true_resid": recs[-1]["true_resid"]},
+                  "true_resid": recs[-1]["true_resid"], "inner_used": recs[-1]["inner_used"]},
     }
     if not args.no_fp64_reference:
         log("bench: FP64 reference solve")

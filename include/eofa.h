@@ -80,6 +80,10 @@ typedef struct {
     double seconds;          /* wall time of the call */
     double flops;            /* operator flops executed (1320 per Wilson hop per 5D site,
                                 72 per bidiagonal 5D op, 144 per inverse 5D op) */
+    eofa_prec_t inner_used[2]; /* the most precise inner arithmetic each system needed: the
+                                  requested one, unless a 16-bit (then FP32) solve stopped
+                                  making progress and continued one precision up (FP16/BF16
+                                  -> FP32 -> FP64) from its current iterate */
 } eofa_stats_t;
 
 /* Create a context for one lattice geometry and gauge field.

@@ -34,11 +34,14 @@ class Solver(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int * 2), ("reliable_updates", C.c_int * 2),
-                ("true_resid", C.c_double * 2), ("seconds", C.c_double), ("flops", C.c_double)]
+                ("true_resid", C.c_double * 2), ("seconds", C.c_double), ("flops", C.c_double),
+                ("inner_used", C.c_int * 2)]
 
     def as_dict(self):
+        names = {v: k for k, v in PREC.items()}
         return {"iters": list(self.iters), "reliable_updates": list(self.reliable_updates),
-                "true_resid": list(self.true_resid), "seconds": self.seconds, "flops": self.flops}
+                "true_resid": list(self.true_resid), "seconds": self.seconds, "flops": self.flops,
+                "inner_used": [names.get(v, str(v)) for v in self.inner_used]}
 
 
 class EOFAError(RuntimeError):

@@ -478,6 +478,7 @@ struct SolveResult {
     int iters = 0;
     int reliable = 0;
     bool converged = false;
+    bool stagnated = false;   // the inner precision stopped making progress (mixed only)
 };
 
 // Solve Mhat x_o = bhat_o by CGNR, x_o holding the initial guess.
@@ -581,6 +582,12 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
         // longer than max(400, 4 x the longest one so far) forces a reliable
         // update and restarts the directions from z.
         int seg_iters = 0, seg_max = 0;
+        // Progress check: a healthy solve halves the true residual every few
+        // dozen iterations.  1000 iterations without halving it force a
+        // reliable update; if that confirms it, the inner precision is
+        // exhausted and the caller continues one precision up.
+        double r_halve = rmax;
+        int it_halve = res.iters;
         while (res.iters < maxiter) {
             Half& p = *pr[k % XBATCH];
             schur_k1(c, prec, p, tmp, mp, mm);
@@ -606,14 +613,16 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
             const double rn = std::sqrt(std::max(rr_est, 0.0));
             ++seg_iters;
             const bool stalled = seg_iters > std::max(400, 4 * seg_max);
+            const bool overdue = res.iters - it_halve > 1000;
             bool restart = false;
-            if (rn <= delta * rmax || rn <= thresh || stalled) {
+            if (rn <= delta * rmax || rn <= thresh || stalled || overdue) {
                 // reliable update: fold the directions into x_lo, x_lo into x, recompute r in FP64
                 flush(k);
                 fold_x();
                 rr = true_residual();
                 check_finite(rr, "true residual");
                 res.reliable++;
+                const double rprev = rmax;
                 rmax = std::sqrt(rr);
                 rr_est = rr;
                 pend_cur = -1;   // the true residual includes iteration k
@@ -621,6 +630,17 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
                 seg_iters = 0;
                 restart = stalled;
                 if (rmax <= thresh) { res.converged = true; break; }
+                if (rmax <= 0.5 * r_halve) {
+                    r_halve = rmax;
+                    it_halve = res.iters;
+                }
+                // a stalled segment (over 400 iterations) that did not even halve
+                // the true residual, or 1000 iterations without halving it: the
+                // inner precision is exhausted here
+                if ((stalled && rmax > 0.5 * rprev) || res.iters - it_halve > 1000) {
+                    res.stagnated = true;
+                    break;
+                }
                 convert(c, r64, r);
                 schur_k3(c, prec, r, tmp, mp, mm);
                 schur_k4(c, prec, tmp, r, z, mp, mm, c->partial);
@@ -681,6 +701,7 @@ struct CayleyOut {
     int iters = 0, reliable = 0;
     double true_resid = 0;
     bool converged = false;
+    int inner_used = P64;   // the most precise inner arithmetic used (after escalations)
 };
 
 void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& Z);
@@ -782,14 +803,15 @@ CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const 
         h.aux2 = &bo; h.cr = 1.0; h.mp = mp; h.mm = mm;
         run_hop(c, h);
     }
-    const int prec = sp.inner;
+    int prec = sp.inner;
+    out.inner_used = prec;
     double thresh = 0.5 * sp.tol * bnorm;
     bool have = guess;
     if (fc && fc->k > 0) {   // chronological guess from earlier solutions (Section 5.2)
         forecast_guess(c, mp, mm, bhat, *fc, yo);
         have = true;
     }
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    for (int attempt = 0; attempt < 6; ++attempt) {
         SolveResult r = cgnr_schur(c, mp, mm, bhat, yo, have, thresh, sp.maxiter - out.iters, prec,
                                    sp.reliable_delta > 0 ? sp.reliable_delta : 0.1);
         out.iters += r.iters;
@@ -821,7 +843,14 @@ CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const 
         check_finite(rr, "true residual");
         out.true_resid = std::sqrt(rr) / bnorm;
         out.converged = out.true_resid <= sp.tol;
-        if (out.converged || !r.converged || out.iters >= sp.maxiter) break;
+        if (out.converged || out.iters >= sp.maxiter) break;
+        if (r.stagnated) {   // continue from y one precision up: 16-bit -> FP32 -> FP64
+            prec = prec == P32 ? P64 : P32;
+            out.inner_used = prec;
+            have = true;
+            continue;
+        }
+        if (!r.converged) break;
         // the recursively updated residual drifted: tighten and continue from y
         thresh *= 0.25 * sp.tol / out.true_resid;
         have = true;
@@ -1031,6 +1060,7 @@ int solve_dense_impl(eofa_ctx* c, double m1, double m2, const void* phi, void* c
             stats->iters[sys] = o.iters;
             stats->reliable_updates[sys] = 0;
             stats->true_resid[sys] = o.true_resid;
+            stats->inner_used[sys] = EOFA_FP64;
         }
         if (!o.converged) status = EOFA_ENOCONV;
     }
@@ -1117,6 +1147,7 @@ int solve_impl(eofa_ctx* c, double m1, double m2, const void* phi, const void* x
             stats->iters[sys] = o.iters;
             stats->reliable_updates[sys] = o.reliable;
             stats->true_resid[sys] = o.true_resid;
+            stats->inner_used[sys] = (eofa_prec_t)o.inner_used;
         }
         if (!o.converged) status = EOFA_ENOCONV;
     }
@@ -1175,7 +1206,10 @@ int heatbath_impl(eofa_ctx* c, double m1, double m2, const void* eta, int n, dou
     }
     const auto t0 = std::chrono::steady_clock::now();
     const double f0 = c->flops;
-    if (stats) *stats = eofa_stats_t{};
+    if (stats) {
+        *stats = eofa_stats_t{};
+        stats->inner_used[0] = stats->inner_used[1] = sp->inner;
+    }
     hipchk(launch_hb_init(eta, phi, c0, (size_t)c->V * 12, c->st), "heatbath");
     int status = EOFA_OK;
     if (k != 0.0 && n > 0) {
@@ -1213,6 +1247,7 @@ int heatbath_impl(eofa_ctx* c, double m1, double m2, const void* eta, int n, dou
                     stats->iters[sys] += o.iters;
                     stats->reliable_updates[sys] += o.reliable;
                     stats->true_resid[sys] = std::max(stats->true_resid[sys], o.true_resid);
+                    stats->inner_used[sys] = (eofa_prec_t)std::min((int)stats->inner_used[sys], o.inner_used);
                 }
                 if (!o.converged) status = EOFA_ENOCONV;
             }
@@ -1252,6 +1287,7 @@ bool apply_meofa(eofa_ctx* c, double m1, double m2, double k, const void* v, voi
             stats->iters[sys] += o.iters;
             stats->reliable_updates[sys] += o.reliable;
             stats->true_resid[sys] = std::max(stats->true_resid[sys], o.true_resid);
+            stats->inner_used[sys] = (eofa_prec_t)std::min((int)stats->inner_used[sys], o.inner_used);
         }
         ok = ok && o.converged;
     }
@@ -1313,7 +1349,10 @@ int bounds_impl(eofa_ctx* c, double m1, double m2, const void* start, int n_iter
     omega_k(c, m1, m2, &k);
     const auto t0 = std::chrono::steady_clock::now();
     const double f0 = c->flops;
-    if (stats) *stats = eofa_stats_t{};
+    if (stats) {
+        *stats = eofa_stats_t{};
+        stats->inner_used[0] = stats->inner_used[1] = sp->inner;
+    }
     const size_t n = (size_t)c->V * 12;
     const size_t bytes = n * 16;
     void* vb[3] = {rawbuf(c, "lz0", bytes), rawbuf(c, "lz1", bytes), rawbuf(c, "lz2", bytes)};
