@@ -158,9 +158,13 @@ def dslash(args):
     from paper_1611_00298_amd import Context
 
     pre = din.preset(args.workload)
+    if args.lattice:
+        pre["L"] = tuple(int(v) for v in args.lattice.split(","))
+    if args.ls:
+        pre["Ls"] = args.ls
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(a).to(dev)
-    log(f"dslash: generating {args.workload} inputs")
+    log(f"dslash: generating {args.workload} inputs {pre['L']} Ls={pre['Ls']}")
     U = t(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"]))
     psi = t(din.gaussian_5d(pre["L"], pre["Ls"], 303))
     ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
@@ -653,6 +657,9 @@ def main():
                     help="hmc: inner force-gradient steps of the gauge dynamics per link update")
     ap.add_argument("--chrono", type=int, default=8,
                     help="hmc: earlier solutions per system for chronological guesses in the MD (0: none)")
+    ap.add_argument("--lattice", default=None,
+                    help="dslash: lattice extents Lx,Ly,Lz,Lt instead of the workload's (volume sweeps)")
+    ap.add_argument("--ls", type=int, default=None, help="dslash: Ls instead of the workload's")
     ap.add_argument("--dense", action="store_true",
                     help="solve on D_EOFA itself (dense 5D blocks) against the Cayley form")
     ap.add_argument("--gauge", action="store_true",
