@@ -78,6 +78,8 @@ int md_blocks(int nlink);
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st);
 hipError_t launch_hop_dense(bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
+hipError_t launch_cg_step64(void* x, const void* p, void* s, const void* w, double alpha, size_t n5, size_t N,
+                            double* partial, int nblk, hipStream_t st);
 int gauge_action_blocks(int V);
 hipError_t launch_gauge_force(const void* U, void* F, const int L[4], double beta, double c1, int accumulate,
                               hipStream_t st);
@@ -999,10 +1001,14 @@ DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& 
         check_finite(ww, "dense CG");
         if (!(ww > 0.0)) break;
         const double alpha = gam / ww;
-        hipchk(launch_caxpy64(xo.d, p.d, alpha, 0.0, c->n5, c->N, c->nblk_blas, c->st), "caxpy");
-        hipchk(launch_caxpy64(sr.d, w.d, -alpha, 0.0, c->n5, c->N, c->nblk_blas, c->st), "caxpy");
+        // x += alpha p ; s -= alpha w ; |s|^2
+        const int ev = timing_begin(c);
+        hipchk(launch_cg_step64(xo.d, p.d, sr.d, w.d, alpha, c->n5, c->N, c->partial, c->nblk_blas, c->st),
+               "cg step");
+        timing_end(c, ev, C_BLAS, (double)c->n5 * 6.0 * spinor_bytes(P64));
+        reduce(c, c->nblk_blas, S_T1);
         ++out.iters;
-        const double ss = norm2(c, sr, S_T1);
+        const double ss = read_slot(c, S_T1);
         check_finite(ss, "dense CG");
         if (std::sqrt(ss) <= target) break;
         mhat_dag(sr, r, c->partial);

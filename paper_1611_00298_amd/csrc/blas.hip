@@ -209,6 +209,31 @@ __global__ void __launch_bounds__(256) k_caxpy64(void* x, const void* y, double 
     }
 }
 
+// CG step of the dense D_EOFA solve (FP64): x += alpha p ; s -= alpha w ;
+// per-workgroup partials of |s|^2 (one pass instead of two axpys and a norm)
+__global__ void __launch_bounds__(256) k_cg_step64(void* x, const void* p, void* s, const void* w, double alpha,
+                                                   size_t n5, size_t N, double* partial) {
+    double acc = 0;
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
+         n += (size_t)gridDim.x * blockDim.x) {
+        double u[24], v[24];
+        ld_spinor<P64>(x, nullptr, N, n, u);
+        ld_spinor<P64>(p, nullptr, N, n, v);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) u[k] = fma(alpha, v[k], u[k]);
+        st_spinor<P64>(x, nullptr, N, n, u);
+        ld_spinor<P64>(s, nullptr, N, n, u);
+        ld_spinor<P64>(w, nullptr, N, n, v);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            u[k] = fma(-alpha, v[k], u[k]);
+            acc = fma(u[k], u[k], acc);
+        }
+        st_spinor<P64>(s, nullptr, N, n, u);
+    }
+    block_store_sum(acc, partial + blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // launchers (grid: a fixed number of workgroups, grid-stride loops)
 // ---------------------------------------------------------------------------
@@ -226,6 +251,12 @@ hipError_t launch_cdot64(const void* a, const void* b, size_t n5, size_t N, doub
 hipError_t launch_caxpy64(void* x, const void* y, double cr, double ci, size_t n5, size_t N, int nblk,
                           hipStream_t st) {
     hipLaunchKernelGGL(k_caxpy64, dim3(nblk), dim3(256), 0, st, x, y, cr, ci, n5, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_step64(void* x, const void* p, void* s, const void* w, double alpha, size_t n5, size_t N,
+                            double* partial, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_step64, dim3(nblk), dim3(256), 0, st, x, p, s, w, alpha, n5, N, partial);
     return hipGetLastError();
 }
 
