@@ -166,3 +166,28 @@ def test_c3_heatbath_property(c3):
     _, _, _, S, _ = ctx.eofa_solve(phi, pre["m1"], pre["m2"], tol=1e-10, inner="fp16", want_mphi=False)
     ee = float(np.vdot(eta, eta).real)
     assert abs(S / ee - 1.0) <= 2 * st["delta"] + 1e-9, (S / ee - 1.0, st["delta"])
+
+
+def test_c3_dense_solve_true_residual_by_oracle(c3):
+    """The dense D_EOFA comparison path (FP64) at 24^3x64, Ls = 24: the
+    oracle recomputes both systems' true residuals |v - H chi| / |v| with its
+    full-lattice H, and the solution agrees with the GPU's Cayley-form solve
+    of the same systems."""
+    import torch
+    pre, lat, U, psi, ctx = c3
+    m1, m2 = pre["m1"], pre["m2"]
+    phi = din.gaussian_4d(pre["L"], pre["seed_phi"])
+    ph = to_dev(phi)
+    chiL, chiR, _, S, st = ctx.eofa_solve_dense(ph, m1, m2, tol=1e-10, want_mphi=False)
+    assert st["converged"] and max(st["true_resid"]) <= 1e-10
+    om_m, om_p, _ = oracle.omega_k(lat, m1, m2)
+    for chi, mm, om, spins in ((chiL, m1, om_m, slice(2, 4)), (chiR, m2, om_p, slice(0, 2))):
+        v = lat.zeros5()
+        v[..., spins, :] = om[:, None, None, None, None, None, None] * phi[None, ..., spins, :]
+        r = oracle.H_op(lat, U, m1, mm, chi.cpu().numpy()) - v
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(v)
+        del r, v
+    cL, cR, _, Sc, _ = ctx.eofa_solve(ph, m1, m2, tol=1e-10, inner="fp16", want_mphi=False)
+    rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    assert rel(chiL, cL) < 1e-8 and rel(chiR, cR) < 1e-8
+    assert abs(S - Sc) <= 1e-10 * abs(Sc)
