@@ -336,6 +336,10 @@ def dense(args):
     res, sols = {}, {}
     runs = (("dense_fp64", lambda: ctx.eofa_solve_dense(phi, m1, m2, tol=1e-10, want_mphi=False)),
             ("cayley_fp64", lambda: ctx.eofa_solve(phi, m1, m2, tol=1e-10, inner="fp64", want_mphi=False)),
+            ("dense_fp32", lambda: ctx.eofa_solve_dense(phi, m1, m2, tol=1e-10, inner="fp32",
+                                                        reliable_delta=args.delta, want_mphi=False)),
+            ("cayley_fp32", lambda: ctx.eofa_solve(phi, m1, m2, tol=1e-10, inner="fp32",
+                                                   reliable_delta=args.delta, want_mphi=False)),
             (f"cayley_{args.inner}", lambda: ctx.eofa_solve(phi, m1, m2, tol=1e-10, inner=args.inner,
                                                            reliable_delta=args.delta, want_mphi=False)))
     for name, run in runs:
@@ -367,6 +371,7 @@ def dense(args):
            "data": "synthetic (random SU(3) links exp(i eps H), Gaussian phi)",
            "solves": res,
            "cayley_fp64_speedup": res["dense_fp64"]["seconds"] / res["cayley_fp64"]["seconds"],
+           "cayley_fp32_speedup": res["dense_fp32"]["seconds"] / res["cayley_fp32"]["seconds"],
            f"cayley_{args.inner}_speedup": res["dense_fp64"]["seconds"] / res[f"cayley_{args.inner}"]["seconds"]}
     if not args.no_cpu_baseline:
         log("dense: CPU oracle baseline")

@@ -132,15 +132,17 @@ class Context:
         d["converged"] = rc == _lib.EOFA_OK
         return chiL, chiR, Mphi, S.value, d
 
-    def eofa_solve_dense(self, phi, m1, m2, tol=1e-10, maxiter=20000, want_mphi=True, allow_noconv=False):
+    def eofa_solve_dense(self, phi, m1, m2, tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.3,
+                         want_mphi=True, allow_noconv=False):
         """The same solves on D_EOFA itself, without the Cayley form (the
-        FP64 comparison path).  Returns (chi_L, chi_R, M_EOFA phi or None, S, stats)."""
+        comparison path; inner "fp64" or "fp32" with reliable updates).
+        Returns (chi_L, chi_R, M_EOFA phi or None, S, stats)."""
         _want(phi, self.shape_phi, "phi")
         chiL = torch.empty(self.shape5, dtype=torch.complex128, device=self.device)
         chiR = torch.empty_like(chiL)
         Mphi = torch.empty_like(phi) if want_mphi else None
         S = C.c_double(0.0)
-        sp = make_solver(tol, maxiter, "fp64", 0.0)
+        sp = make_solver(tol, maxiter, inner, reliable_delta)
         st = Stats()
         rc = self.lib.eofa_solve_dense(self.handle, float(m1), float(m2), _ptr(phi), _ptr(chiL), _ptr(chiR),
                                        _ptr(Mphi), C.byref(S), C.byref(sp), C.byref(st))

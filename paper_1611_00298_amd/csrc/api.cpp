@@ -77,9 +77,9 @@ hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, con
 int md_blocks(int nlink);
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st);
-hipError_t launch_hop_dense(bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
-hipError_t launch_cg_step64(void* x, const void* p, void* s, const void* w, double alpha, size_t n5, size_t N,
-                            double* partial, int nblk, hipStream_t st);
+hipError_t launch_hop_dense(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
+hipError_t launch_cg_step(int prec, void* x, const void* p, void* s, const void* w, double alpha, size_t n5,
+                          size_t N, double* partial, int nblk, hipStream_t st);
 int gauge_action_blocks(int V);
 hipError_t launch_gauge_force(const void* U, void* F, const int L[4], double beta, double c1, int accumulate,
                               hipStream_t st);
@@ -344,10 +344,10 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     if (h.hop) bytes += 72.0 * complex_bytes(h.prec) * c->Vh;
     const int ev = timing_begin(c);
     if (h.dmat) {
-        if (h.prec != P64 || h.C.kind != 0 || h.B2.kind != 0 || h.dev_alpha)
+        if ((h.prec != P64 && h.prec != P32) || h.C.kind != 0 || h.B2.kind != 0 || h.dev_alpha)
             fail(EOFA_EDEVICE, "internal: unsupported dense hop form");
         a.dmat = h.dmat;
-        hipchk(launch_hop_dense(h.dag, h.hop, a, c->nblk_hop, c->st), "dense hop kernel");
+        hipchk(launch_hop_dense(h.prec, h.dag, h.hop, a, c->nblk_hop, c->st), "dense hop kernel");
         timing_end(c, ev, h.hop ? C_HOPDENSE : C_BLAS, bytes);
         return;
     }
@@ -943,20 +943,27 @@ std::vector<double> dense_blocks(const eofa_ctx* c, double mp, double mm) {
 
 struct DenseOut {
     int iters = 0;
+    int reliable = 0;
     double true_resid = 0;
     bool converged = false;
 };
 
-// Dense hop forms: out = ch DA(Dh in) + ca DB(aux) + cr aux2 on output parity par
-void dense_hop(eofa_ctx* c, const double* dm, bool dag, int par, const Half* in, Half& out, Op5 A, double ch,
-               const Half* aux, Op5 B, double ca, const Half* aux2, double cr, double* partial) {
+// Dense hop forms in precision prec: out = ch DA(Dh in) + ca DB(aux) + cr aux2 on output parity par
+void dense_hop(eofa_ctx* c, const double* dm, int prec, bool dag, int par, const Half* in, Half& out, Op5 A,
+               double ch, const Half* aux, Op5 B, double ca, const Half* aux2, double cr, double* partial) {
     HopCall h;
-    h.prec = P64; h.dag = dag; h.hop = in != nullptr; h.par = par; h.in = in; h.out = &out;
+    h.prec = prec; h.dag = dag; h.hop = in != nullptr; h.par = par; h.in = in; h.out = &out;
     h.A = A; h.ch = ch; h.aux = aux; h.B = B; h.ca = ca; h.aux2 = aux2; h.cr = cr;
     h.partial = partial; h.dmat = dm;
     run_hop(c, h);
 }
 
+// Even-odd CGNR on Mhat = D5 - Dh_oe D5^-1 Dh_eo.  sp.inner = FP64: plain
+// CGNR.  FP32: the same recursion in FP32 storage and arithmetic (x summed
+// in FP32 too) with reliable updates, as in the Cayley-form solver: when
+// the recursive |s| falls below delta times the true residual of the last
+// update, x is folded into the FP64 solution and s = bhat - Mhat x is
+// recomputed in FP64.
 DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& bo, Half& xe, Half& xo,
                      const eofa_solver_t& sp) {
     DenseOut out;
@@ -969,31 +976,42 @@ DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& 
         return out;
     }
     const double bnorm = std::sqrt(b2);
-    Half& t = ws(c, "dn_t", P64);
+    const int prec = sp.inner == EOFA_FP32 ? P32 : P64;
+    const bool mixed = prec != P64;
+    Half& t64 = ws(c, "dn_t", P64);
     Half& bh = ws(c, "dn_bhat", P64);
-    Half& sr = ws(c, "dn_s", P64);   // s = bhat - Mhat x_o
-    Half& r = ws(c, "dn_r", P64);    // r = Mhat^dag s
-    Half& p = ws(c, "dn_p", P64);
-    Half& w = ws(c, "dn_w", P64);
+    Half& s64 = ws(c, "dn_s", P64);
     // bhat_o = b_o - Dh_oe D5^-1 b_e
-    dense_hop(c, dm, false, 0, nullptr, t, I5, 1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
-    dense_hop(c, dm, false, 1, &t, bh, I5, -1.0, nullptr, I5, 0.0, &bo, 1.0, nullptr);
+    dense_hop(c, dm, P64, false, 0, nullptr, t64, I5, 1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
+    dense_hop(c, dm, P64, false, 1, &t64, bh, I5, -1.0, nullptr, I5, 0.0, &bo, 1.0, nullptr);
     zero(c, xo);
+    Half& t = ws(c, "dn_t", prec);
+    Half& sr = ws(c, "dn_s", prec);   // s = bhat - Mhat x_o (its recursion)
+    Half& r = ws(c, "dn_r", prec);    // r = Mhat^dag s
+    Half& p = ws(c, "dn_p", prec);
+    Half& w = ws(c, "dn_w", prec);
+    Half& xl = mixed ? ws(c, "dn_xlo", P32) : xo;   // where the iterations sum x
+    if (mixed) zero(c, xl);
     convert(c, bh, sr);
     auto mhat = [&](const Half& in, Half& o, double* partial) {   // o = Mhat in
-        dense_hop(c, dm, false, 0, &in, t, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
-        dense_hop(c, dm, false, 1, &t, o, I5, -1.0, &in, D5(0), 1.0, nullptr, 0.0, partial);
+        dense_hop(c, dm, prec, false, 0, &in, t, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+        dense_hop(c, dm, prec, false, 1, &t, o, I5, -1.0, &in, D5(0), 1.0, nullptr, 0.0, partial);
     };
     auto mhat_dag = [&](const Half& in, Half& o, double* partial) {   // o = Mhat^dag in
-        dense_hop(c, dm, true, 0, &in, t, D5Inv(1), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
-        dense_hop(c, dm, true, 1, &t, o, I5, -1.0, &in, D5(1), 1.0, nullptr, 0.0, partial);
+        dense_hop(c, dm, prec, true, 0, &in, t, D5Inv(1), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+        dense_hop(c, dm, prec, true, 1, &t, o, I5, -1.0, &in, D5(1), 1.0, nullptr, 0.0, partial);
     };
+    auto fold = [&]() {   // x_o += x_lo, x_lo = 0
+        hipchk(launch_accum_hi(P32, xo.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+    };
+    const double target = sp.tol * bnorm;
+    const double delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.1;
+    double rmax = std::sqrt(norm2(c, bh, S_T1));   // true residual at the last reliable update
     mhat_dag(sr, r, c->partial);
     reduce(c, nb, S_T0);
     double gam = read_slot(c, S_T0);
     check_finite(gam, "dense CG");
     convert(c, r, p);
-    const double target = sp.tol * bnorm;
     while (out.iters < sp.maxiter && gam > 0.0) {
         mhat(p, w, c->partial);
         reduce(c, nb, S_T0);
@@ -1003,28 +1021,41 @@ DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& 
         const double alpha = gam / ww;
         // x += alpha p ; s -= alpha w ; |s|^2
         const int ev = timing_begin(c);
-        hipchk(launch_cg_step64(xo.d, p.d, sr.d, w.d, alpha, c->n5, c->N, c->partial, c->nblk_blas, c->st),
+        hipchk(launch_cg_step(prec, xl.d, p.d, sr.d, w.d, alpha, c->n5, c->N, c->partial, c->nblk_blas, c->st),
                "cg step");
-        timing_end(c, ev, C_BLAS, (double)c->n5 * 6.0 * spinor_bytes(P64));
+        timing_end(c, ev, C_BLAS, (double)c->n5 * 6.0 * spinor_bytes(prec));
         reduce(c, c->nblk_blas, S_T1);
         ++out.iters;
-        const double ss = read_slot(c, S_T1);
-        check_finite(ss, "dense CG");
-        if (std::sqrt(ss) <= target) break;
+        double rn = std::sqrt(read_slot(c, S_T1));
+        check_finite(rn, "dense CG");
+        if (mixed && (rn <= delta * rmax || rn <= target)) {
+            // reliable update: s = bhat - Mhat x in FP64 (Mhat x = D5 x - Dh_oe D5^-1 Dh_eo x)
+            fold();
+            dense_hop(c, dm, P64, false, 0, &xo, t64, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+            dense_hop(c, dm, P64, false, 1, &t64, s64, I5, 1.0, &xo, D5(0), -1.0, &bh, 1.0, c->partial);
+            reduce(c, nb, S_T1);
+            const double rr = read_slot(c, S_T1);
+            check_finite(rr, "true residual");
+            rmax = rn = std::sqrt(rr);
+            ++out.reliable;
+            convert(c, s64, sr);
+        }
+        if (rn <= target) break;
         mhat_dag(sr, r, c->partial);
         reduce(c, nb, S_T0);
         const double g2 = read_slot(c, S_T0);
         check_finite(g2, "dense CG");
         // p <- r + (g2 / gam) p
-        dense_hop(c, dm, false, 0, nullptr, p, I5, 1.0, &p, I5, g2 / gam, &r, 1.0, nullptr);
+        dense_hop(c, dm, prec, false, 0, nullptr, p, I5, 1.0, &p, I5, g2 / gam, &r, 1.0, nullptr);
         gam = g2;
     }
+    if (mixed) fold();
     // x_e = D5^-1 (b_e - Dh_eo x_o)
-    dense_hop(c, dm, false, 0, &xo, xe, D5Inv(0), -1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
+    dense_hop(c, dm, P64, false, 0, &xo, xe, D5Inv(0), -1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
     // true residual of the full system: b_p - D5 x_p - Dh x_pbar
     Half& rt = ws(c, "rt", P64);
     for (int par = 0; par < 2; ++par)
-        dense_hop(c, dm, false, par, par ? &xe : &xo, rt, I5, -1.0, par ? &xo : &xe, D5(0), -1.0,
+        dense_hop(c, dm, P64, false, par, par ? &xe : &xo, rt, I5, -1.0, par ? &xo : &xe, D5(0), -1.0,
                   par ? &bo : &be, 1.0, c->partial + (size_t)par * nb);
     reduce(c, 2 * nb, S_T0);
     const double rr = read_slot(c, S_T0);
@@ -1038,7 +1069,8 @@ int solve_dense_impl(eofa_ctx* c, double m1, double m2, const void* phi, void* c
                      double* S, const eofa_solver_t* sp, eofa_stats_t* stats) {
     if (!c || !phi || !chiL || !chiR) fail(EOFA_EINVAL, "NULL argument");
     validate_solver(sp);
-    if (sp->inner != EOFA_FP64) fail(EOFA_EINVAL, "the dense D_EOFA path runs in FP64 only");
+    if (sp->inner != EOFA_FP64 && sp->inner != EOFA_FP32)
+        fail(EOFA_EINVAL, "the dense D_EOFA path runs with FP64 or FP32 inner arithmetic");
     if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
     double k;
     omega_k(c, m1, m2, &k);
@@ -1064,9 +1096,9 @@ int solve_dense_impl(eofa_ctx* c, double m1, double m2, const void* phi, void* c
         hipchk(launch_dev_to_nat5(sys ? chiR : chiL, ce.d, co.d, c->L, c->Ls, c->N, c->st), "layout");
         if (stats) {
             stats->iters[sys] = o.iters;
-            stats->reliable_updates[sys] = 0;
+            stats->reliable_updates[sys] = o.reliable;
             stats->true_resid[sys] = o.true_resid;
-            stats->inner_used[sys] = EOFA_FP64;
+            stats->inner_used[sys] = sp->inner;
         }
         if (!o.converged) status = EOFA_ENOCONV;
     }

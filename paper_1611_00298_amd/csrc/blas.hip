@@ -209,27 +209,31 @@ __global__ void __launch_bounds__(256) k_caxpy64(void* x, const void* y, double 
     }
 }
 
-// CG step of the dense D_EOFA solve (FP64): x += alpha p ; s -= alpha w ;
-// per-workgroup partials of |s|^2 (one pass instead of two axpys and a norm)
-__global__ void __launch_bounds__(256) k_cg_step64(void* x, const void* p, void* s, const void* w, double alpha,
-                                                   size_t n5, size_t N, double* partial) {
+// CG step of the dense D_EOFA solve (FP64, or FP32 inside the mixed solve):
+// x += alpha p ; s -= alpha w ; per-workgroup partials of |s|^2 in FP64
+// (one pass instead of two axpys and a norm)
+template <int P>
+__global__ void __launch_bounds__(256) k_cg_step(void* x, const void* p, void* s, const void* w, double alpha_d,
+                                                 size_t n5, size_t N, double* partial) {
+    using A = typename PT<P>::A;
+    const A alpha = (A)alpha_d;
     double acc = 0;
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
          n += (size_t)gridDim.x * blockDim.x) {
-        double u[24], v[24];
-        ld_spinor<P64>(x, nullptr, N, n, u);
-        ld_spinor<P64>(p, nullptr, N, n, v);
+        A u[24], v[24];
+        ld_spinor<P>(x, nullptr, N, n, u);
+        ld_spinor<P>(p, nullptr, N, n, v);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) u[k] = fma(alpha, v[k], u[k]);
-        st_spinor<P64>(x, nullptr, N, n, u);
-        ld_spinor<P64>(s, nullptr, N, n, u);
-        ld_spinor<P64>(w, nullptr, N, n, v);
+        for (int k = 0; k < 24; ++k) u[k] = fmadd(alpha, v[k], u[k]);
+        st_spinor<P>(x, nullptr, N, n, u);
+        ld_spinor<P>(s, nullptr, N, n, u);
+        ld_spinor<P>(w, nullptr, N, n, v);
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
-            u[k] = fma(-alpha, v[k], u[k]);
-            acc = fma(u[k], u[k], acc);
+            u[k] = fmadd(-alpha, v[k], u[k]);
+            acc = fma((double)u[k], (double)u[k], acc);
         }
-        st_spinor<P64>(s, nullptr, N, n, u);
+        st_spinor<P>(s, nullptr, N, n, u);
     }
     block_store_sum(acc, partial + blockIdx.x);
 }
@@ -254,9 +258,14 @@ hipError_t launch_caxpy64(void* x, const void* y, double cr, double ci, size_t n
     return hipGetLastError();
 }
 
-hipError_t launch_cg_step64(void* x, const void* p, void* s, const void* w, double alpha, size_t n5, size_t N,
-                            double* partial, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_step64, dim3(nblk), dim3(256), 0, st, x, p, s, w, alpha, n5, N, partial);
+hipError_t launch_cg_step(int prec, void* x, const void* p, void* s, const void* w, double alpha, size_t n5,
+                          size_t N, double* partial, int nblk, hipStream_t st) {
+    if (prec == P64)
+        hipLaunchKernelGGL(k_cg_step<P64>, dim3(nblk), dim3(256), 0, st, x, p, s, w, alpha, n5, N, partial);
+    else if (prec == P32)
+        hipLaunchKernelGGL(k_cg_step<P32>, dim3(nblk), dim3(256), 0, st, x, p, s, w, alpha, n5, N, partial);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

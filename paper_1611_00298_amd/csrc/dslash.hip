@@ -916,20 +916,30 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     return hipGetLastError();
 }
 
-// FP64 hop with dense 5D blocks (kind-3 Op5s), for D_EOFA's even-odd form
-template <bool DAG, bool HOP>
+// FP64 or FP32 hop with dense 5D blocks (kind-3 Op5s), for D_EOFA's even-odd form
+template <int P, bool DAG, bool HOP>
 static hipError_t launch_hop_dense_t(const HopArgs& a, int nblk, hipStream_t st) {
+    using A = typename PT<P>::A;
     const int NT = a.NS * a.Ls;
-    const size_t tile = (size_t)STR * NT * sizeof(double);
-    const size_t shm = HOP ? std::max(tile, stage_bytes(LinkLds<P64, 0>::LB, a.NS)) : tile;
-    hipLaunchKernelGGL((k_hop<P64, DAG, HOP, 0, true>), dim3(nblk), dim3(NT), shm, st, a);
+    const size_t tile = (size_t)STR * NT * sizeof(A);
+    const size_t shm = HOP ? std::max(tile, stage_bytes(LinkLds<P, 0>::LB, a.NS)) : tile;
+    hipLaunchKernelGGL((k_hop<P, DAG, HOP, 0, true>), dim3(nblk), dim3(NT), shm, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_hop_dense(bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st) {
+hipError_t launch_hop_dense(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st) {
     if (!a.dmat) return hipErrorInvalidValue;
-    if (hop) return dag ? launch_hop_dense_t<true, true>(a, nblk, st) : launch_hop_dense_t<false, true>(a, nblk, st);
-    return launch_hop_dense_t<false, false>(a, nblk, st);
+    if (prec == P64) {
+        if (hop) return dag ? launch_hop_dense_t<P64, true, true>(a, nblk, st)
+                            : launch_hop_dense_t<P64, false, true>(a, nblk, st);
+        return launch_hop_dense_t<P64, false, false>(a, nblk, st);
+    }
+    if (prec == P32) {
+        if (hop) return dag ? launch_hop_dense_t<P32, true, true>(a, nblk, st)
+                            : launch_hop_dense_t<P32, false, true>(a, nblk, st);
+        return launch_hop_dense_t<P32, false, false>(a, nblk, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_hop(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st) {
