@@ -8,7 +8,11 @@
  *   2. eofa_solve with the FP16 inner solver: the true residual reported,
  *      S against the oracle's action on the same chi (eq. (2.5)), and S
  *      against the oracle's own Cayley-form solve;
- *   3. error paths: m1 > m2 and a NULL context give EOFA_EINVAL with a message.
+ *   3. the gauge action and force (zero on unit links), the dense D_EOFA
+ *      solve (same action), the force (finite), the MD update (kinetic
+ *      term), and the heatbath on a Lanczos interval (phi^dag M phi =
+ *      eta^dag eta within the approximation error);
+ *   4. error paths: m1 > m2 and a NULL context give EOFA_EINVAL with a message.
  *
  * Prints "abi_check: ok" and exits 0, or names the failed check and exits 1.
  */
@@ -163,7 +167,67 @@ int main(void) {
     orc_action(&og, m1, m2, phi, rL, rR, S2, NULL);
     CHECK(fabs(S - S2[0]) <= 1e-9 * fabs(S2[0]), "S = %.15e, oracle %.15e", S, S2[0]);
 
-    /* 3. error paths */
+    /* 3. the other entry points, each with a property that fixes its answer */
+    {
+        /* gauge action and force of unit links: exactly zero */
+        double *one = calloc(nU, sizeof(double));
+        for (size_t l = 0; l < (size_t)4 * V; ++l)
+            for (int a = 0; a < 3; ++a) one[18 * l + 8 * a] = 1.0;
+        void *done = dev_copy(one, nU), *dF = dev_copy(NULL, nU);
+        double Sg = -1;
+        rc = eofa_gauge_action(ctx, done, 2.13, -0.331, &Sg);
+        CHECK(rc == EOFA_OK && Sg == 0.0, "gauge action of unit links: %d %g", rc, Sg);
+        rc = eofa_gauge_force(ctx, done, 2.13, -0.331, dF, 0);
+        hipMemcpy(one, dF, nU * sizeof(double), hipMemcpyDeviceToHost);
+        double fbig = 0;
+        for (size_t i = 0; i < nU; ++i) fbig = fbig > fabs(one[i]) ? fbig : fabs(one[i]);
+        CHECK(rc == EOFA_OK && fbig == 0.0, "gauge force of unit links: %d %g", rc, fbig);
+        rc = eofa_gauge_action(ctx, dU, 2.13, -0.331, &Sg);
+        CHECK(rc == EOFA_OK && Sg > 0.0 && isfinite(Sg), "gauge action of random links: %d %g", rc, Sg);
+
+        /* the dense D_EOFA path (FP32 inner) solves the same systems */
+        eofa_solver_t sp32 = {1e-10, 20000, EOFA_FP32, 0.3};
+        double Sd = 0;
+        rc = eofa_solve_dense(ctx, m1, m2, dphi, dchiL, dchiR, NULL, &Sd, &sp32, &st);
+        CHECK(rc == EOFA_OK && fabs(Sd - S) <= 1e-9 * fabs(S), "dense solve: %d %.15e vs %.15e", rc, Sd, S);
+
+        /* the force from those solutions is finite */
+        rc = eofa_force(ctx, m1, m2, dphi, dchiL, dchiR, dF, NULL, &sp, NULL);
+        hipMemcpy(one, dF, nU * sizeof(double), hipMemcpyDeviceToHost);
+        int fin = 1;
+        for (size_t i = 0; i < nU; ++i) fin = fin && isfinite(one[i]);
+        CHECK(rc == EOFA_OK && fin, "force: %d", rc);
+
+        /* MD update with dt = 0: only the kinetic term, P and U untouched */
+        double *P = calloc(nU, sizeof(double)), kin = -1;
+        for (size_t l = 0; l < (size_t)4 * V; ++l) { P[18 * l] = 0.5; P[18 * l + 8] = -0.5; }   /* diag(1/2, -1/2, 0) */
+        void *dP = dev_copy(P, nU);
+        rc = eofa_md_update(ctx, dU, dP, NULL, 0.0, 0.0, &kin);
+        CHECK(rc == EOFA_OK && fabs(kin - 0.5 * 4 * V) <= 1e-12 * V, "md kinetic: %d %g", rc, kin);
+
+        /* heatbath of eq. (3.1): phi^dag M_EOFA phi = eta^dag eta up to the
+         * approximation error on an interval from the Lanczos bounds */
+        double th[2], res[2];
+        eofa_solver_t spb = {1e-8, 20000, EOFA_FP64, 0.3};
+        rc = eofa_meofa_bounds(ctx, m1, m2, dphi, 20, &spb, th, res, NULL);
+        CHECK(rc == EOFA_OK && th[0] > 0 && th[1] > th[0], "meofa bounds: %d %g %g", rc, th[0], th[1]);
+        double a0, al[8], be[8], delta;
+        const double lo = 0.9 * fmax(th[0] - res[0], 0.5 * th[0]), hi = 1.1 * (th[1] + res[1]);
+        rc = eofa_rational_inv_sqrt(lo, hi, 6, &a0, al, be, &delta);
+        CHECK(rc == EOFA_OK, "rational coefficients: %d", rc);
+        void *deta = dev_copy(phi, n4), *dphi2 = dev_copy(NULL, n4);
+        rc = eofa_heatbath(ctx, m1, m2, deta, 6, a0, al, be, 4, dphi2, &sp, &st);
+        CHECK(rc == EOFA_OK, "heatbath: %d %s", rc, eofa_last_error());
+        double Sh = 0, ee = 0;
+        rc = eofa_solve(ctx, m1, m2, dphi2, NULL, NULL, dchiL, dchiR, NULL, &Sh, &sp, &st);
+        for (size_t i = 0; i < n4; ++i) ee += phi[i] * phi[i];
+        CHECK(rc == EOFA_OK && fabs(Sh / ee - 1.0) <= 2.01 * delta + 1e-8,
+              "heatbath: S/eta^2 - 1 = %.3e, delta %.3e", Sh / ee - 1.0, delta);
+        hipFree(done); hipFree(dF); hipFree(dP); hipFree(deta); hipFree(dphi2);
+        free(one); free(P);
+    }
+
+    /* 4. error paths */
     rc = eofa_solve(ctx, m2, m1, dphi, NULL, NULL, dchiL, dchiR, NULL, &S, &sp, &st);
     CHECK(rc == EOFA_EINVAL && strlen(eofa_last_error()) > 0, "m1 > m2 not rejected: %d", rc);
     CHECK(dwf_apply(NULL, 0.1, 0.1, 0, 0, EOFA_FP64, dpsi, dout) == EOFA_EINVAL, "NULL context not rejected");
