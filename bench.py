@@ -340,6 +340,8 @@ def dense(args):
                                                         reliable_delta=args.delta, want_mphi=False)),
             ("cayley_fp32", lambda: ctx.eofa_solve(phi, m1, m2, tol=1e-10, inner="fp32",
                                                    reliable_delta=args.delta, want_mphi=False)),
+            ("dense_fp16", lambda: ctx.eofa_solve_dense(phi, m1, m2, tol=1e-10, inner="fp16",
+                                                        reliable_delta=args.delta, want_mphi=False)),
             (f"cayley_{args.inner}", lambda: ctx.eofa_solve(phi, m1, m2, tol=1e-10, inner=args.inner,
                                                            reliable_delta=args.delta, want_mphi=False)))
     for name, run in runs:
@@ -370,9 +372,11 @@ def dense(args):
                                   f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}: both systems"},
            "data": "synthetic (random SU(3) links exp(i eps H), Gaussian phi)",
            "solves": res,
-           "cayley_fp64_speedup": res["dense_fp64"]["seconds"] / res["cayley_fp64"]["seconds"],
-           "cayley_fp32_speedup": res["dense_fp32"]["seconds"] / res["cayley_fp32"]["seconds"],
-           f"cayley_{args.inner}_speedup": res["dense_fp64"]["seconds"] / res[f"cayley_{args.inner}"]["seconds"]}
+           }
+    # same inner precision on both sides: dense time / Cayley-form time
+    for pr in ("fp64", "fp32", "fp16"):
+        if f"dense_{pr}" in res and f"cayley_{pr}" in res:
+            out[f"cayley_{pr}_speedup"] = res[f"dense_{pr}"]["seconds"] / res[f"cayley_{pr}"]["seconds"]
     if not args.no_cpu_baseline:
         log("dense: CPU oracle baseline")
         out["cpu_baseline"] = dense_cpu_baseline()

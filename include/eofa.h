@@ -130,8 +130,9 @@ int eofa_solve(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
  * D5 applied as one Ls x Ls block per chirality.  The residual
  * b - D_EOFA chi equals the Cayley form's b - D_DWF y (chi = Dtilde y), so
  * `solver->tol` means the same in both.  solver->inner: EOFA_FP64 (plain
- * CGNR) or EOFA_FP32 (FP32 recursion with FP64 reliable updates, as in
- * eofa_solve); the 16-bit formats give EOFA_EINVAL.  No initial guesses.
+ * CGNR), EOFA_FP32 or EOFA_FP16 (that storage with FP32 arithmetic and FP64
+ * reliable updates, as in eofa_solve); EOFA_BF16 gives EOFA_EINVAL.  No
+ * initial guesses or precision escalation.
  * Arguments, outputs and errors as in eofa_solve. */
 int eofa_solve_dense(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev, void *chiL_dev,
                      void *chiR_dev, void *Mphi_dev, double *S_out, const eofa_solver_t *solver,

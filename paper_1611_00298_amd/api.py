@@ -135,7 +135,7 @@ class Context:
     def eofa_solve_dense(self, phi, m1, m2, tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.3,
                          want_mphi=True, allow_noconv=False):
         """The same solves on D_EOFA itself, without the Cayley form (the
-        comparison path; inner "fp64" or "fp32" with reliable updates).
+        comparison path; inner "fp64", "fp32" or "fp16" with reliable updates).
         Returns (chi_L, chi_R, M_EOFA phi or None, S, stats)."""
         _want(phi, self.shape_phi, "phi")
         chiL = torch.empty(self.shape5, dtype=torch.complex128, device=self.device)

@@ -78,8 +78,9 @@ int md_blocks(int nlink);
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st);
 hipError_t launch_hop_dense(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
-hipError_t launch_cg_step(int prec, void* x, const void* p, void* s, const void* w, double alpha, size_t n5,
-                          size_t N, double* partial, int nblk, hipStream_t st);
+hipError_t launch_cg_step(int prec, void* x, const void* p, const float* pn, void* s, float* sn, const void* w,
+                          const float* wn, double alpha, size_t n5, size_t N, double* partial, int nblk,
+                          hipStream_t st);
 int gauge_action_blocks(int V);
 hipError_t launch_gauge_force(const void* U, void* F, const int L[4], double beta, double c1, int accumulate,
                               hipStream_t st);
@@ -344,7 +345,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     if (h.hop) bytes += 72.0 * complex_bytes(h.prec) * c->Vh;
     const int ev = timing_begin(c);
     if (h.dmat) {
-        if ((h.prec != P64 && h.prec != P32) || h.C.kind != 0 || h.B2.kind != 0 || h.dev_alpha)
+        if ((h.prec != P64 && h.prec != P32 && h.prec != P16) || h.C.kind != 0 || h.B2.kind != 0 || h.dev_alpha)
             fail(EOFA_EDEVICE, "internal: unsupported dense hop form");
         a.dmat = h.dmat;
         hipchk(launch_hop_dense(h.prec, h.dag, h.hop, a, c->nblk_hop, c->st), "dense hop kernel");
@@ -959,8 +960,9 @@ void dense_hop(eofa_ctx* c, const double* dm, int prec, bool dag, int par, const
 }
 
 // Even-odd CGNR on Mhat = D5 - Dh_oe D5^-1 Dh_eo.  sp.inner = FP64: plain
-// CGNR.  FP32: the same recursion in FP32 storage and arithmetic (x summed
-// in FP32 too) with reliable updates, as in the Cayley-form solver: when
+// CGNR.  FP32 or FP16 (+ site norm): the same recursion in that storage with
+// FP32 arithmetic (x summed in FP32) and reliable updates, as in the
+// Cayley-form solver: when
 // the recursive |s| falls below delta times the true residual of the last
 // update, x is folded into the FP64 solution and s = bhat - Mhat x is
 // recomputed in FP64.
@@ -976,7 +978,7 @@ DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& 
         return out;
     }
     const double bnorm = std::sqrt(b2);
-    const int prec = sp.inner == EOFA_FP32 ? P32 : P64;
+    const int prec = sp.inner == EOFA_FP32 ? P32 : sp.inner == EOFA_FP16 ? P16 : P64;
     const bool mixed = prec != P64;
     Half& t64 = ws(c, "dn_t", P64);
     Half& bh = ws(c, "dn_bhat", P64);
@@ -1021,7 +1023,8 @@ DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& 
         const double alpha = gam / ww;
         // x += alpha p ; s -= alpha w ; |s|^2
         const int ev = timing_begin(c);
-        hipchk(launch_cg_step(prec, xl.d, p.d, sr.d, w.d, alpha, c->n5, c->N, c->partial, c->nblk_blas, c->st),
+        hipchk(launch_cg_step(prec, xl.d, p.d, p.nrm, sr.d, sr.nrm, w.d, w.nrm, alpha, c->n5, c->N, c->partial,
+                              c->nblk_blas, c->st),
                "cg step");
         timing_end(c, ev, C_BLAS, (double)c->n5 * 6.0 * spinor_bytes(prec));
         reduce(c, c->nblk_blas, S_T1);
@@ -1069,8 +1072,7 @@ int solve_dense_impl(eofa_ctx* c, double m1, double m2, const void* phi, void* c
                      double* S, const eofa_solver_t* sp, eofa_stats_t* stats) {
     if (!c || !phi || !chiL || !chiR) fail(EOFA_EINVAL, "NULL argument");
     validate_solver(sp);
-    if (sp->inner != EOFA_FP64 && sp->inner != EOFA_FP32)
-        fail(EOFA_EINVAL, "the dense D_EOFA path runs with FP64 or FP32 inner arithmetic");
+    if (sp->inner == EOFA_BF16) fail(EOFA_EINVAL, "the dense D_EOFA path has no BF16 inner solver");
     if (!(m1 <= m2)) fail(EOFA_EINVAL, "EOFA needs m1 <= m2");
     double k;
     omega_k(c, m1, m2, &k);

@@ -212,28 +212,33 @@ __global__ void __launch_bounds__(256) k_caxpy64(void* x, const void* y, double 
 // CG step of the dense D_EOFA solve (FP64, or FP32 inside the mixed solve):
 // x += alpha p ; s -= alpha w ; per-workgroup partials of |s|^2 in FP64
 // (one pass instead of two axpys and a norm)
-template <int P>
-__global__ void __launch_bounds__(256) k_cg_step(void* x, const void* p, void* s, const void* w, double alpha_d,
-                                                 size_t n5, size_t N, double* partial) {
+// x is held in PX (FP32 when p, s and w are 16-bit); FP16 fields carry their
+// per-site norms
+template <int P, int PX>
+__global__ void __launch_bounds__(256) k_cg_step(void* x, const void* p, const float* pn, void* s, float* sn,
+                                                 const void* w, const float* wn, double alpha_d, size_t n5,
+                                                 size_t N, double* partial) {
     using A = typename PT<P>::A;
+    using AX = typename PT<PX>::A;
     const A alpha = (A)alpha_d;
     double acc = 0;
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
          n += (size_t)gridDim.x * blockDim.x) {
         A u[24], v[24];
-        ld_spinor<P>(x, nullptr, N, n, u);
-        ld_spinor<P>(p, nullptr, N, n, v);
+        AX xv[24];
+        ld_spinor<PX>(x, nullptr, N, n, xv);
+        ld_spinor<P>(p, pn, N, n, v);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) u[k] = fmadd(alpha, v[k], u[k]);
-        st_spinor<P>(x, nullptr, N, n, u);
-        ld_spinor<P>(s, nullptr, N, n, u);
-        ld_spinor<P>(w, nullptr, N, n, v);
+        for (int k = 0; k < 24; ++k) xv[k] = fmadd((AX)alpha, (AX)v[k], xv[k]);
+        st_spinor<PX>(x, nullptr, N, n, xv);
+        ld_spinor<P>(s, sn, N, n, u);
+        ld_spinor<P>(w, wn, N, n, v);
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
             u[k] = fmadd(-alpha, v[k], u[k]);
             acc = fma((double)u[k], (double)u[k], acc);
         }
-        st_spinor<P>(s, nullptr, N, n, u);
+        st_spinor<P>(s, sn, N, n, u);
     }
     block_store_sum(acc, partial + blockIdx.x);
 }
@@ -258,12 +263,18 @@ hipError_t launch_caxpy64(void* x, const void* y, double cr, double ci, size_t n
     return hipGetLastError();
 }
 
-hipError_t launch_cg_step(int prec, void* x, const void* p, void* s, const void* w, double alpha, size_t n5,
-                          size_t N, double* partial, int nblk, hipStream_t st) {
+hipError_t launch_cg_step(int prec, void* x, const void* p, const float* pn, void* s, float* sn, const void* w,
+                          const float* wn, double alpha, size_t n5, size_t N, double* partial, int nblk,
+                          hipStream_t st) {
     if (prec == P64)
-        hipLaunchKernelGGL(k_cg_step<P64>, dim3(nblk), dim3(256), 0, st, x, p, s, w, alpha, n5, N, partial);
+        hipLaunchKernelGGL((k_cg_step<P64, P64>), dim3(nblk), dim3(256), 0, st, x, p, pn, s, sn, w, wn, alpha, n5,
+                           N, partial);
     else if (prec == P32)
-        hipLaunchKernelGGL(k_cg_step<P32>, dim3(nblk), dim3(256), 0, st, x, p, s, w, alpha, n5, N, partial);
+        hipLaunchKernelGGL((k_cg_step<P32, P32>), dim3(nblk), dim3(256), 0, st, x, p, pn, s, sn, w, wn, alpha, n5,
+                           N, partial);
+    else if (prec == P16)
+        hipLaunchKernelGGL((k_cg_step<P16, P32>), dim3(nblk), dim3(256), 0, st, x, p, pn, s, sn, w, wn, alpha, n5,
+                           N, partial);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -666,7 +666,7 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 }
 
 template <int P, bool DAG, bool HOP, int MF, bool DENSE = false>
-__global__ void __launch_bounds__(256, (MF == 3 && P == P16) ? 5 : 3) k_hop(const HopArgs a) {
+__global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) k_hop(const HopArgs a) {
     using A = typename PT<P>::A;
     // column-sweep load batch: what each variant's register budget allows
     constexpr int COLB = P == P64 ? 1 : (P == P16 && MF) ? 4 : 8;
@@ -916,12 +916,22 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     return hipGetLastError();
 }
 
-// FP64 or FP32 hop with dense 5D blocks (kind-3 Op5s), for D_EOFA's even-odd form
+// Hop with dense 5D blocks (kind-3 Op5s), for D_EOFA's even-odd form: FP64,
+// FP32, or FP16 (matrix cores when the compact links are given)
 template <int P, bool DAG, bool HOP>
 static hipError_t launch_hop_dense_t(const HopArgs& a, int nblk, hipStream_t st) {
     using A = typename PT<P>::A;
     const int NT = a.NS * a.Ls;
     const size_t tile = (size_t)STR * NT * sizeof(A);
+    if constexpr (P == P16 && HOP) {
+        if (a.frag) {
+            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 1>::LB, a.NS));
+            if (a.depth >= 4) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 4, true>), dim3(nblk), dim3(NT), shm, st, a);
+            else if (a.depth == 3) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 3, true>), dim3(nblk), dim3(NT), shm, st, a);
+            else hipLaunchKernelGGL((k_hop<P, DAG, HOP, 2, true>), dim3(nblk), dim3(NT), shm, st, a);
+            return hipGetLastError();
+        }
+    }
     const size_t shm = HOP ? std::max(tile, stage_bytes(LinkLds<P, 0>::LB, a.NS)) : tile;
     hipLaunchKernelGGL((k_hop<P, DAG, HOP, 0, true>), dim3(nblk), dim3(NT), shm, st, a);
     return hipGetLastError();
@@ -938,6 +948,11 @@ hipError_t launch_hop_dense(int prec, bool dag, bool hop, const HopArgs& a, int 
         if (hop) return dag ? launch_hop_dense_t<P32, true, true>(a, nblk, st)
                             : launch_hop_dense_t<P32, false, true>(a, nblk, st);
         return launch_hop_dense_t<P32, false, false>(a, nblk, st);
+    }
+    if (prec == P16) {
+        if (hop) return dag ? launch_hop_dense_t<P16, true, true>(a, nblk, st)
+                            : launch_hop_dense_t<P16, false, true>(a, nblk, st);
+        return launch_hop_dense_t<P16, false, false>(a, nblk, st);
     }
     return hipErrorInvalidValue;
 }
