@@ -673,7 +673,6 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) 
     extern __shared__ unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
     __shared__ double red[16];
-    const int NT = blockDim.x;
     const int tid = threadIdx.x;
     const int Ls = a.Ls;
     const int sl = tid / Ls;
@@ -845,7 +844,6 @@ __global__ void __launch_bounds__(256) k_pupdate(const void* z, const float* z_n
     using A = typename PT<P>::A;
     extern __shared__ unsigned char smem_raw[];
     A* lds = reinterpret_cast<A*>(smem_raw);
-    const int NT = blockDim.x;
     const int tid = threadIdx.x;
     const int sl = tid / Ls;
     const int s = tid - sl * Ls;
