@@ -517,6 +517,65 @@ def test_md_exponential():
     assert oracle.kinetic(P) == pytest.approx(0.5 * (p ** 2).sum(), rel=1e-12)
 
 
+def _md_hamiltonian(U, P, beta, c1):
+    return oracle.kinetic(P) + oracle.gauge_action(U, beta, c1)
+
+
+def _leapfrog(U, P, beta, c1, n, dt, update):
+    """n leapfrog steps of length dt, each call of `update` kicking P with
+    the force at the current links and then drifting U with the new P."""
+    U, P = update(U, P, oracle.gauge_force(U, beta, c1), 0.5 * dt, dt)
+    for _ in range(1, n):
+        U, P = update(U, P, oracle.gauge_force(U, beta, c1), dt, dt)
+    return update(U, P, oracle.gauge_force(U, beta, c1), 0.5 * dt, 0.0)
+
+
+def _md_pin(update):
+    """Energy error at three step sizes over a fixed trajectory length, and
+    the distance of a forward-then-reversed trajectory from its start."""
+    L, beta, c1, tau = (4, 4, 4, 4), 5.7, 0.0, 0.5
+    U0 = din.random_gauge(L, 0.5, 131)
+    P0 = din.gaussian_momenta(L, 132)
+    H0 = _md_hamiltonian(U0, P0, beta, c1)
+    dH = []
+    for n in (4, 8, 16):
+        U, P = _leapfrog(U0, P0, beta, c1, n, tau / n, update)
+        dH.append(_md_hamiltonian(U, P, beta, c1) - H0)
+        if n == 8:
+            Ur, Pr = _leapfrog(U, -P, beta, c1, n, tau / n, update)
+            rev = max(np.abs(Ur - U0).max(), np.abs(Pr + P0).max())
+    return dH, rev
+
+
+def test_md_update_leapfrog():
+    """HMC molecular dynamics (Section 3) with the oracle's update and its
+    finite-difference-pinned gauge force: the equations of motion
+    dU/dt = iPU, dP/dt = -F conserve H = tr P^2 + S_g, so leapfrog's energy
+    error falls as dt^2 (a factor of 4 per halving), and the integrator is
+    reversible: flipping P and integrating again returns to (U0, -P0)."""
+    dH, rev = _md_pin(oracle.md_update)
+    for a, b in zip(dH, dH[1:]):
+        assert 3.0 < a / b < 5.0, dH
+    assert rev < 1e-12
+
+
+def test_md_update_pin_detects_planted_mistakes():
+    """The leapfrog pin above fails for the two plausible slips in the
+    update: the wrong sign of the force kick (P + dt F) and a drift that
+    uses the momenta from before the kick."""
+    def wrong_sign(U, P, F, dt_p, dt_u):
+        P = P + dt_p * F
+        return oracle.expi_hermitian(dt_u * P) @ U, P
+
+    def stale_momenta(U, P, F, dt_p, dt_u):
+        return oracle.expi_hermitian(dt_u * P) @ U, P - dt_p * F
+
+    for update in (wrong_sign, stale_momenta):
+        dH, rev = _md_pin(update)
+        scales = all(3.0 < a / b < 5.0 for a, b in zip(dH, dH[1:]))
+        assert not (scales and rev < 1e-12), update.__name__
+
+
 # --------------------------------------------------------------------------
 # heatbath (Section 3.2, eq. (3.1))
 # --------------------------------------------------------------------------
