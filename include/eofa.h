@@ -231,6 +231,29 @@ int eofa_force(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
 int eofa_md_update(eofa_ctx_t *ctx, void *U_dev, void *P_dev, const void *F_dev,
                    double dt_p, double dt_u, double *kinetic_out);
 
+/* Allocation-free variant of eofa_md_update, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving or
+ * molecular-dynamics loops, harnesses that forbid hipMalloc.  It performs
+ * the same update with the same kernels and allocates nothing (no hipMalloc,
+ * hipFree or allocating library call) and never synchronises:
+ *   P <- P - dt_p F   (skipped if F_dev is NULL or dt_p == 0)
+ *   U <- exp(i dt_u P) U  (skipped if dt_u == 0)
+ *   *kinetic_dev = sum over links tr(P^2)   (NULL: skip)
+ * kinetic_dev: one double in device memory (the caller's), written on the
+ * context stream; it equals eofa_md_update's kinetic_out bit for bit.
+ * The block partials of the kinetic sum live in a static device array of
+ * 16384 doubles (128 KiB) that each GPU holds until the process ends, so a
+ * kinetic sum needs V <= 1048576 4D sites (EOFA_EINVAL otherwise; without
+ * kinetic_dev any size works).  All calls on one GPU share that array and
+ * it keeps the last call's partials: calls with kinetic_dev that can
+ * overlap on one GPU (different streams or threads without ordering) race.
+ * Calls on one stream are ordered and safe.  No timing is recorded.
+ * The context must have been created (eofa_ctx_create takes the array's
+ * device address once per GPU).  Errors: EOFA_EINVAL (NULL ctx, U or P;
+ * too large a lattice), EOFA_EDEVICE (launch failure). */
+int eofa_md_update_noalloc(eofa_ctx_t *ctx, void *U_dev, void *P_dev, const void *F_dev,
+                           double dt_p, double dt_u, double *kinetic_dev);
+
 /* Gauge action of the ensembles the paper runs on (Table 1: Iwasaki), FP64:
  *   S_g = beta sum_x [ c0 sum_{mu<nu} (1 - Re tr W_1x1(x)/3)
  *                    + c1 sum_{mu!=nu} (1 - Re tr W_2x1(x)/3) ],  c0 = 1 - 8 c1,

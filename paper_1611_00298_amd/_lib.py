@@ -16,7 +16,7 @@ PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 
 EXPORTS = [
     "eofa_ctx_create", "eofa_ctx_destroy", "eofa_ctx_update_gauge", "dwf_apply", "eofa_solve", "eofa_solve_dense",
-    "eofa_force", "eofa_md_update", "eofa_rational_inv_sqrt", "eofa_heatbath", "eofa_meofa_bounds", "eofa_chrono",
+    "eofa_force", "eofa_md_update", "eofa_md_update_noalloc", "eofa_rational_inv_sqrt", "eofa_heatbath", "eofa_meofa_bounds", "eofa_chrono",
     "eofa_gauge_action", "eofa_gauge_force", "eofa_timing_enable",
     "eofa_timing_query", "eofa_last_error",
 ]
@@ -72,6 +72,7 @@ def load() -> C.CDLL:
                                   C.POINTER(Stats)]),
         "eofa_force": (I_, [P, D, D, P, P, P, P, P, C.POINTER(Solver), C.POINTER(Stats)]),
         "eofa_md_update": (I_, [P, P, P, P, D, D, C.POINTER(C.c_double)]),
+        "eofa_md_update_noalloc": (I_, [P, P, P, P, D, D, P]),
         "eofa_rational_inv_sqrt": (I_, [D, D, I_, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "eofa_heatbath": (I_, [P, D, D, P, I_, D, C.POINTER(C.c_double), C.POINTER(C.c_double), I_, P,

@@ -234,6 +234,21 @@ class Context:
                                       float(dt_u), C.byref(kin)))
         return kin.value
 
+    def md_update_noalloc(self, U, P, F=None, dt_p=0.0, dt_u=0.0, kinetic=None):
+        """eofa_md_update_noalloc: the same in-place update, asynchronous and
+        allocation-free; with `kinetic` (a float64 CUDA tensor of one
+        element) sum tr P^2 is written there on the device."""
+        _want(U, self.shape_gauge, "U")
+        _want(P, self.shape_gauge, "P")
+        _want(F, self.shape_gauge, "F")
+        if kinetic is not None:
+            if (not isinstance(kinetic, torch.Tensor) or kinetic.device.type != "cuda"
+                    or kinetic.dtype != torch.float64 or kinetic.numel() < 1):
+                raise TypeError("kinetic must be a float64 CUDA tensor with at least one element")
+        check(self.lib.eofa_md_update_noalloc(self.handle, _ptr(U), _ptr(P), _ptr(F), float(dt_p),
+                                              float(dt_u), _ptr(kinetic)))
+        return kinetic
+
     # -- gauge action (Table 1: Iwasaki; c1 = 0 is Wilson) -----------------------
     def gauge_action(self, U, beta, c1=IWASAKI_C1):
         """S_g of the field U (any field of this geometry), FP64."""

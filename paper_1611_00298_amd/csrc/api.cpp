@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,6 +76,7 @@ hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, con
                         const void* chiRo, const int* nbr, const int* sites, double k, void* F, void* G,
                         const int L[4], int Ls, int aperiodic, int NS, int nblk, size_t N, hipStream_t st);
 int md_blocks(int nlink);
+hipError_t md_scratch_address(double** out);
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st);
 hipError_t launch_hop_dense(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
@@ -126,6 +128,27 @@ struct TimingRec {
     int ev;
     double bytes;
 };
+
+// Device address of the MD update's static scratch array, per GPU, taken
+// once per device at context creation with that device current.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+void init_scratch(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) fail(EOFA_EDEVICE, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return;
+    double* p = nullptr;
+    hipchk(md_scratch_address(&p), "hipGetSymbolAddress(scratch)");
+    if (!p) fail(EOFA_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch[dev] = p;
+}
+
+double* scratch_of(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return dev >= 0 && dev < MAX_DEVICES ? g_scratch[dev] : nullptr;
+}
 
 }  // namespace
 
@@ -1607,6 +1630,7 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
         eofa_ctx* c = new eofa_ctx();
         try {
             hipchk(hipGetDevice(&c->dev), "hipGetDevice");
+            init_scratch(c->dev);
             c->st = (hipStream_t)stream;
             for (int mu = 0; mu < 4; ++mu) c->L[mu] = g->L[mu];
             c->Ls = g->Ls;
@@ -1840,6 +1864,27 @@ int eofa_md_update(eofa_ctx_t* c, void* U, void* P, const void* F, double dt_p, 
             reduce(c, md_blocks(nlink), S_T1);
             *kin = read_slot(c, S_T1);
         }
+        return EOFA_OK;
+    });
+}
+
+int eofa_md_update_noalloc(eofa_ctx_t* c, void* U, void* P, const void* F, double dt_p, double dt_u,
+                           double* kin_dev) {
+    return guarded([&]() -> int {
+        if (!c || !U || !P) fail(EOFA_EINVAL, "NULL argument");
+        const int nlink = 4 * c->V;
+        double* scr = nullptr;
+        if (kin_dev) {
+            if (md_blocks(nlink) > MD_SCRATCH_DOUBLES)
+                fail(EOFA_EINVAL, "lattice too large for eofa_md_update_noalloc: at most " +
+                                      std::to_string((long)MD_SCRATCH_DOUBLES * 64) + " sites");
+            scr = scratch_of(c->dev);
+            if (!scr) fail(EOFA_EDEVICE, "scratch address not initialised for this device");
+        }
+        // the same kernels as eofa_md_update; every partial the reduction
+        // reads is written by this call first, so nothing needs clearing
+        hipchk(launch_md_update(U, P, F, dt_p, dt_u, nlink, scr, c->st), "md update");
+        if (kin_dev) hipchk(launch_reduce(scr, md_blocks(nlink), kin_dev, 0, c->st), "reduce");
         return EOFA_OK;
     });
 }

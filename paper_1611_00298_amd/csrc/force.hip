@@ -258,6 +258,17 @@ hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, con
 
 int md_blocks(int nlink) { return (nlink + 255) / 256; }
 
+// Scratch of the allocation-free MD update: the per-block partial sums of
+// tr P^2 that k_md_update writes and k_reduce adds up.  Each GPU holds its
+// own copy for the life of the process.  In host code the name below is not
+// a device address: the host reaches the array only through the pointer
+// md_scratch_address returns (hipGetSymbolAddress on the current device).
+static __device__ __align__(256) double scratch[MD_SCRATCH_DOUBLES];
+
+hipError_t md_scratch_address(double** out) {
+    return hipGetSymbolAddress((void**)out, HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_md_update(void* U, void* P, const void* F, double dt_p, double dt_u, int nlink,
                             double* partial, hipStream_t st) {
     hipLaunchKernelGGL(k_md_update, dim3(md_blocks(nlink)), dim3(256), 0, st, (double2*)U, (double2*)P,

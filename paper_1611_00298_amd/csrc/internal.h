@@ -199,6 +199,11 @@ __device__ __forceinline__ float ld_spinor_raw(const void* __restrict__ base, co
 // ---------------------------------------------------------------------------
 constexpr int link_prec(int p) { return p == P64 ? P64 : P32; }
 
+// Size of the static scratch array of the allocation-free MD update, in
+// doubles: one partial sum per 256 links, so lattices of up to 2^20 4D
+// sites (128 KiB per GPU).
+constexpr int MD_SCRATCH_DOUBLES = 16384;
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumber them so that XCD x works on one contiguous range of
 // logical blocks (neighbouring 4D sites then share an L2).

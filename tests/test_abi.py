@@ -64,6 +64,7 @@ def test_null_arguments_are_rejected():
     assert lib.eofa_force(None, 0.1, 0.2, None, None, None, None, None, C.byref(sp),
                           None) == _lib.EOFA_EINVAL
     assert lib.eofa_md_update(None, None, None, None, 0.0, 0.0, None) == _lib.EOFA_EINVAL
+    assert lib.eofa_md_update_noalloc(None, None, None, None, 0.0, 0.0, None) == _lib.EOFA_EINVAL
     assert lib.eofa_heatbath(None, 0.1, 0.2, None, 0, 1.0, None, None, 0, None, C.byref(sp),
                              None) == _lib.EOFA_EINVAL
     assert lib.eofa_meofa_bounds(None, 0.1, 0.2, None, 10, C.byref(sp), None, None,
