@@ -13,6 +13,22 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def region_rel(a, b):
+    """Largest relative L2 error over the thin regions of a 5D field
+    (s, t, z, y, x, spin, colour) where the boundary terms act: the s-wrap
+    slices s = 0 and s = Ls - 1, and the time faces t = 0 and t = Lt - 1,
+    each measured against its own norm (an error confined to one of them
+    would vanish in the norm of the whole field)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    worst = 0.0
+    for idx in ((0,), (b.shape[0] - 1,), (slice(None), 0), (slice(None), b.shape[1] - 1)):
+        nb = np.linalg.norm(b[idx])
+        if nb > 0:
+            worst = max(worst, float(np.linalg.norm(a[idx] - b[idx]) / nb))
+    return worst
+
+
 # stated parity bounds for the reduced-precision operator (a few unit roundoffs)
 PREC_TOL = {"fp64": 1e-12, "fp32": 1e-6, "fp16": 2e-3, "bf16": 2e-2}
 

@@ -31,17 +31,63 @@ def c3():
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def boundary_sites(lat, n, parity, seed):
+    """(s, site) pairs of the given parity on the s-wrap slices (s = 0 or
+    Ls - 1) or on the t-boundary faces (t = 0 or Lt - 1), where the 5D
+    wrap masses and the antiperiodic time links act."""
+    rng = np.random.default_rng(seed)
+    par = lat.parity_mask().reshape(-1)
+    Lx, Ly, Lz, Lt = lat.L
+    t = np.arange(lat.V) // (Lx * Ly * Lz)
+    face = np.nonzero((par == parity) & ((t == 0) | (t == Lt - 1)))[0]
+    anyp = np.nonzero(par == parity)[0]
+    half = n // 2
+    s_wrap = np.stack([rng.choice([0, lat.Ls - 1], size=half), rng.choice(anyp, size=half)], 1)
+    t_face = np.stack([rng.integers(lat.Ls, size=n - half), rng.choice(face, size=n - half)], 1)
+    return np.concatenate([s_wrap, t_face])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_c3_sampled_schur(c3, prec, dagger):
-    """Mhat (the operator inside the CG, launched as in bench.py) at 64 odd sites."""
+    """Mhat (the operator inside the CG, launched as in bench.py) at 64 odd
+    sites anywhere, and separately at 64 odd sites on the s-wrap slices and
+    the t-boundary faces, each set within the stated bound of its own norm,
+    so that an error confined to those thin regions cannot hide in the
+    bulk; every sampled site also within 4x the bound of its own norm."""
     pre, lat, U, psi, ctx = c3
     m1 = pre["m1"]
     out = ctx.dwf_apply(to_dev(psi), m1, 1.0, dagger=dagger, eo=True, prec=prec)
-    sites = sample_sites(lat, 64, 1, 11)
-    got = out.view(lat.Ls, lat.V, 4, 3)[sites[:, 0], sites[:, 1]].cpu().numpy()
-    ref = oracle.schur_sites(lat, U, m1, 1.0, psi, sites, dagger=dagger)
-    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < PREC_TOL[prec]
+    view = out.view(lat.Ls, lat.V, 4, 3)
+    for sites in (sample_sites(lat, 64, 1, 11), boundary_sites(lat, 64, 1, 13)):
+        got = view[sites[:, 0], sites[:, 1]].cpu().numpy()
+        ref = oracle.schur_sites(lat, U, m1, 1.0, psi, sites, dagger=dagger)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < PREC_TOL[prec]
+        per_site = np.linalg.norm((got - ref).reshape(len(sites), -1), axis=1) / \
+            np.linalg.norm(ref.reshape(len(sites), -1), axis=1)
+        assert per_site.max() < 4 * PREC_TOL[prec], per_site.max()
+
+
+def test_c3_fp16_solve_true_residual_by_oracle(c3):
+    """The benchmarked solve (24^3x64, Ls = 24, FP16 inner with reliable
+    updates, delta = 0.3, true residual 1e-10): the oracle recomputes both
+    systems' |v - H chi| / |v| with its full-lattice H, including chi_R's
+    H(m1, m2) = H(m2) - Delta_+ P_+."""
+    pre, lat, U, psi, ctx = c3
+    m1, m2 = pre["m1"], pre["m2"]
+    phi = din.gaussian_4d(pre["L"], pre["seed_phi"])
+    chiL, chiR, _, S, st = ctx.eofa_solve(to_dev(phi), m1, m2, tol=1e-10, inner="fp16",
+                                          reliable_delta=0.3, want_mphi=False)
+    assert st["converged"] and max(st["true_resid"]) <= 1e-10
+    om_m, om_p, _ = oracle.omega_k(lat, m1, m2)
+    for i, (chi, mm, om, spins) in enumerate(((chiL, m1, om_m, slice(2, 4)), (chiR, m2, om_p, slice(0, 2)))):
+        v = lat.zeros5()
+        v[..., spins, :] = om[:, None, None, None, None, None, None] * phi[None, ..., spins, :]
+        res = np.linalg.norm(oracle.H_op(lat, U, m1, mm, chi.cpu().numpy()) - v) / np.linalg.norm(v)
+        print(f"c3 fp16 solve: system {i}: oracle residual {res:.3e}, GPU {st['true_resid'][i]:.3e}")
+        assert res <= 1e-10
+        assert abs(res - st["true_resid"][i]) <= 0.05 * res + 1e-14
+        del v
 
 
 @pytest.mark.parametrize("dagger", [False, True])
@@ -102,12 +148,14 @@ def c2():
 
 def test_c2_solves_true_residual_by_oracle(c2):
     """FP64 and FP16-mixed solves at 16^3x32x16: the oracle recomputes
-    |v - H chi| / |v| with the dense-D_perp definition of H."""
+    |v - H chi| / |v| of both systems with the dense-D_perp definition of H."""
     pre, lat, U, phi, ctx = c2
     m1, m2 = pre["m1"], pre["m2"]
     om_m, om_p, k = oracle.omega_k(lat, m1, m2)
     vL = lat.zeros5()
     vL[..., 2:, :] = om_m[:, None, None, None, None, None, None] * phi[None, ..., 2:, :]
+    vR = lat.zeros5()
+    vR[..., :2, :] = om_p[:, None, None, None, None, None, None] * phi[None, ..., :2, :]
     S = {}
     for inner in ("fp64", "fp16"):
         chiL, chiR, _, S[inner], st = ctx.eofa_solve(to_dev(phi), m1, m2, tol=1e-10, inner=inner,
@@ -116,6 +164,10 @@ def test_c2_solves_true_residual_by_oracle(c2):
         res = np.linalg.norm(vL - oracle.H_op(lat, U, m1, m1, chiL.cpu().numpy())) / np.linalg.norm(vL)
         assert res <= 1e-10
         assert abs(res - st["true_resid"][0]) <= 0.05 * res + 1e-14
+        # chi_R solves H(m1, m2) = H(m2) - Delta_+ P_+ (the mass split of the R system)
+        resR = np.linalg.norm(vR - oracle.H_op(lat, U, m1, m2, chiR.cpu().numpy())) / np.linalg.norm(vR)
+        assert resR <= 1e-10
+        assert abs(resR - st["true_resid"][1]) <= 0.05 * resR + 1e-14
     assert abs(S["fp16"] - S["fp64"]) <= 1e-9 * abs(S["fp64"])
 
 
@@ -168,18 +220,21 @@ def test_c3_heatbath_property(c3):
     assert abs(S / ee - 1.0) <= 2 * st["delta"] + 1e-9, (S / ee - 1.0, st["delta"])
 
 
-def test_c3_dense_solve_true_residual_by_oracle(c3):
-    """The dense D_EOFA comparison path (FP64) at 24^3x64, Ls = 24: the
-    oracle recomputes both systems' true residuals |v - H chi| / |v| with its
-    full-lattice H, and the solution agrees with the GPU's Cayley-form solve
-    of the same systems."""
+@pytest.mark.parametrize("inner", ["fp64", "fp16"])
+def test_c3_dense_solve_true_residual_by_oracle(c3, inner):
+    """The dense D_EOFA comparison path (FP64, and FP16 inner solves with
+    FP64 reliable updates as timed against the Cayley form) at 24^3x64,
+    Ls = 24: the oracle recomputes both systems' true residuals
+    |v - H chi| / |v| with its full-lattice H, and the solution agrees with
+    the GPU's Cayley-form solve of the same systems."""
     import torch
     pre, lat, U, psi, ctx = c3
     m1, m2 = pre["m1"], pre["m2"]
     phi = din.gaussian_4d(pre["L"], pre["seed_phi"])
     ph = to_dev(phi)
-    chiL, chiR, _, S, st = ctx.eofa_solve_dense(ph, m1, m2, tol=1e-10, want_mphi=False)
+    chiL, chiR, _, S, st = ctx.eofa_solve_dense(ph, m1, m2, tol=1e-10, inner=inner, want_mphi=False)
     assert st["converged"] and max(st["true_resid"]) <= 1e-10
+    assert st["inner_used"] == [inner, inner], st
     om_m, om_p, _ = oracle.omega_k(lat, m1, m2)
     for chi, mm, om, spins in ((chiL, m1, om_m, slice(2, 4)), (chiR, m2, om_p, slice(0, 2))):
         v = lat.zeros5()

@@ -5,7 +5,7 @@ import pytest
 
 import dwf_inputs as din
 import oracle
-from helpers import PREC_TOL, rel, to_dev
+from helpers import PREC_TOL, region_rel, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,7 @@ def test_ddwf_parity(setup, prec, dagger, masses):
     out = ctx.dwf_apply(to_dev(psi), mp, mm, dagger=dagger, prec=prec).cpu().numpy()
     ref = oracle.ddwf(lat, U, mp, mm, psi, dagger=dagger)
     assert rel(out, ref) < PREC_TOL[prec]
+    assert region_rel(out, ref) < PREC_TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
@@ -56,6 +57,7 @@ def test_schur_parity(setup, prec, dagger, masses):
     even = (lat.parity_mask() == 0)[None, ..., None, None]
     assert np.abs(out * even).max() == 0.0
     assert rel(out, ref) < PREC_TOL[prec]
+    assert region_rel(out, ref) < PREC_TOL[prec]
 
 
 def test_adjoint_identity_gpu(setup):
