@@ -351,7 +351,7 @@ def dense(args):
         chiL, chiR, _, S, st = run()
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
-        cls = "hop64_dense" if name.startswith("dense") else "hop"
+        cls = "hop_dense" if name.startswith("dense") else "hop"
         q = ctx.timing_query(cls)
         ctx.timing_enable(False)
         sols[name] = (chiL, chiR)
@@ -822,7 +822,24 @@ def main():
         cl, cr = last["chi"]
         out["solve"]["mixed_vs_fp64"] = {"chi_L_rel": rel(cl, chiL64), "chi_R_rel": rel(cr, chiR64),
                                          "S_rel": abs(recs[-1]["S"] - S64) / abs(S64)}
-        del chiL64, chiR64
+        # the mixed solver's own iteration (recursive z folded into the last
+        # hop, Cayley-form directions, scalars read one iteration late,
+        # reliable updates) run entirely in FP64: the speed-up over it is
+        # that of the reduced-precision arithmetic alone
+        log("bench: fused FP64 reference solve")
+        restart()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        chiLf, chiRf, _, Sf, stf = ctx.eofa_solve(phi, m1, m2, want_mphi=False, tol=tol, inner="fp64_fused",
+                                                  reliable_delta=args.delta)
+        torch.cuda.synchronize()
+        out["solve"]["fp64_fused_s"] = time.perf_counter() - t3
+        out["solve"]["fp64_fused_iters"] = stf["iters"]
+        out["solve"]["fp64_fused_true_resid"] = stf["true_resid"]
+        out["solve"]["speedup_mixed_vs_fp64_fused"] = out["solve"]["fp64_fused_s"] / out["solve"]["mixed_s"]
+        out["solve"]["fp64_fused_vs_fp64"] = {"chi_L_rel": rel(chiLf, chiL64), "chi_R_rel": rel(chiRf, chiR64),
+                                              "S_rel": abs(Sf - S64) / abs(S64)}
+        del chiL64, chiR64, chiLf, chiRf
     ctx.close()
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")

@@ -71,6 +71,16 @@ typedef struct {
     int maxiter;           /* limit on inner CG iterations per system */
     eofa_prec_t inner;     /* EOFA_FP64: plain CGNR; else reliable-update mixed precision */
     double reliable_delta; /* reliable update when |r| falls below delta * |r| at the last update */
+    int fused_fp64;        /* inner == EOFA_FP64 only (ignored otherwise).  0: plain CGNR, which
+                              updates r, recomputes z = Mhat^dag r and reads |r|^2 on the host
+                              every iteration.  1: the iteration of the mixed-precision solver run
+                              entirely in FP64: z follows its own recursion inside the last hop
+                              launch, the directions are kept as Dtilde p, the host reads the
+                              scalars one iteration late, and FP64 reliable updates (every
+                              reliable_delta of residual reduction) recompute the true residual.
+                              It isolates the gain of the 16-bit and FP32 inner arithmetic from
+                              that of these fusions.  eofa_solve, eofa_force, eofa_heatbath and
+                              eofa_meofa_bounds honour it; eofa_solve_dense ignores it. */
 } eofa_solver_t;
 
 typedef struct {
@@ -132,7 +142,10 @@ int eofa_solve(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev,
  * `solver->tol` means the same in both.  solver->inner: EOFA_FP64 (plain
  * CGNR), EOFA_FP32 or EOFA_FP16 (that storage with FP32 arithmetic and FP64
  * reliable updates, as in eofa_solve); EOFA_BF16 gives EOFA_EINVAL.  No
- * initial guesses or precision escalation.
+ * initial guesses.  A 16-bit (then FP32) inner solve that stops making
+ * progress (no halving of the true residual in 1000 iterations, or a
+ * stalled segment between reliable updates) continues one precision up
+ * from its iterate, as in eofa_solve; stats->inner_used reports it.
  * Arguments, outputs and errors as in eofa_solve. */
 int eofa_solve_dense(eofa_ctx_t *ctx, double m1, double m2, const void *phi_dev, void *chiL_dev,
                      void *chiR_dev, void *Mphi_dev, double *S_out, const eofa_solver_t *solver,
@@ -280,8 +293,9 @@ int eofa_gauge_force(eofa_ctx_t *ctx, const void *U_dev, double beta, double c1,
  * eofa_timing_query synchronises and returns, for kernel class `name`
  * ("hop" = the 5D hopping kernel in any precision, "hop64", "hop32",
  * "hop16", "hopb16", "blas", "force", "md", "gauge_force",
- * "gauge_action", "hop64_dense"), the launch count, the summed
- * duration in ms and the summed algorithmic bytes. */
+ * "gauge_action", "hop_dense" = the hopping kernel of eofa_solve_dense in
+ * any of its precisions), the launch count, the summed duration in ms and
+ * the summed algorithmic bytes. */
 int eofa_timing_enable(eofa_ctx_t *ctx, int on);
 int eofa_timing_query(eofa_ctx_t *ctx, const char *name, long *count, double *ms, double *bytes);
 

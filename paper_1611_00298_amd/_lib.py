@@ -29,7 +29,7 @@ class Geom(C.Structure):
 
 class Solver(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("inner", C.c_int),
-                ("reliable_delta", C.c_double)]
+                ("reliable_delta", C.c_double), ("fused_fp64", C.c_int)]
 
 
 class Stats(C.Structure):

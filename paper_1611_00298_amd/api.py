@@ -38,7 +38,11 @@ def _want(t, shape, name):
 
 
 def make_solver(tol=1e-10, maxiter=20000, inner="fp64", reliable_delta=0.3) -> Solver:
-    return Solver(float(tol), int(maxiter), PREC[inner], float(reliable_delta))
+    """inner: "fp64" (plain CGNR), "fp32", "fp16", "bf16", or "fp64_fused"
+    (the mixed-precision iteration run in FP64: eofa_solver_t.fused_fp64)."""
+    if inner == "fp64_fused":
+        return Solver(float(tol), int(maxiter), PREC["fp64"], float(reliable_delta), 1)
+    return Solver(float(tol), int(maxiter), PREC[inner], float(reliable_delta), 0)
 
 
 def rational_inv_sqrt(lo, hi, n):

@@ -121,7 +121,7 @@ struct Half {
 enum Cls { C_HOP64 = 0, C_HOP32, C_HOP16, C_HOPB16, C_BLAS, C_FORCE, C_MD, C_GFORCE, C_GACTION, C_HOPDENSE,
            C_NCLS };
 const char* cls_name[C_NCLS] = {"hop64", "hop32", "hop16", "hopb16", "blas", "force", "md",
-                                "gauge_force", "gauge_action", "hop64_dense"};
+                                "gauge_force", "gauge_action", "hop_dense"};
 
 struct TimingRec {
     int cls;
@@ -295,7 +295,7 @@ struct HopCall {
     // ch and ca scaled on the device by sc[s_num] / sc[s_den] (saved to sc[s_alpha])
     bool dev_alpha = false;
     int s_num = 0, s_den = 0, s_alpha = -1;
-    // dense blocks [D5+, D5-, D5inv+, D5inv-] (FP64 dense comparison path only)
+    // dense blocks [D5+, D5-, D5inv+, D5inv-] (the dense D_EOFA path, any of its precisions)
     const double* dmat = nullptr;
 };
 
@@ -508,10 +508,12 @@ struct SolveResult {
 };
 
 // Solve Mhat x_o = bhat_o by CGNR, x_o holding the initial guess.
-// Stops when |bhat - Mhat x| <= thresh.  prec == P64: plain FP64 CGNR.
-// Otherwise: reliable-update mixed precision with an inner precision `prec`.
+// Stops when |bhat - Mhat x| <= thresh.  prec == P64 without `fused`: plain
+// FP64 CGNR.  Otherwise the reliable-update iteration with inner precision
+// `prec` (with prec == P64 and `fused`: the same iteration, every step in
+// FP64, so that it differs from the plain CGNR only by its fusions).
 SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half& x, bool guess,
-                       double thresh, int maxiter, int prec, double delta) {
+                       double thresh, int maxiter, int prec, double delta, bool fused = false) {
     SolveResult res;
     const int nb = c->nblk_hop;
     Half& tmp64 = ws(c, "tmp_e", P64);
@@ -540,8 +542,8 @@ SolveResult cgnr_schur(eofa_ctx* c, double mp, double mm, const Half& bhat, Half
     check_finite(rr, "residual norm");
     if (std::sqrt(rr) <= thresh) { res.converged = true; return res; }
 
-    const bool mixed = prec != P64;
-    const int px = mixed ? P32 : P64;
+    const bool mixed = prec != P64 || fused;
+    const int px = prec != P64 ? P32 : P64;
     Half& r = mixed ? ws(c, "r_lo", prec) : r64;
     Half& z = ws(c, "z", prec);
     Half* pr[XBATCH];   // ring of search directions p_k (buffer k mod XBATCH)
@@ -830,6 +832,7 @@ CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const 
         run_hop(c, h);
     }
     int prec = sp.inner;
+    bool fused = prec == P64 && sp.fused_fp64 != 0;
     out.inner_used = prec;
     double thresh = 0.5 * sp.tol * bnorm;
     bool have = guess;
@@ -839,7 +842,7 @@ CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const 
     }
     for (int attempt = 0; attempt < 6; ++attempt) {
         SolveResult r = cgnr_schur(c, mp, mm, bhat, yo, have, thresh, sp.maxiter - out.iters, prec,
-                                   sp.reliable_delta > 0 ? sp.reliable_delta : 0.1);
+                                   sp.reliable_delta > 0 ? sp.reliable_delta : 0.1, fused);
         out.iters += r.iters;
         out.reliable += r.reliable;
         // y_e = M_ee^-1 (b_e - Dh_eo Dtilde y_o)
@@ -871,7 +874,8 @@ CayleyOut solve_cayley(eofa_ctx* c, double mp, double mm, const Half& be, const 
         out.converged = out.true_resid <= sp.tol;
         if (out.converged || out.iters >= sp.maxiter) break;
         if (r.stagnated) {   // continue from y one precision up: 16-bit -> FP32 -> FP64
-            prec = prec == P32 ? P64 : P32;
+            if (prec == P64) fused = false;   // fused FP64 stalled: the plain CGNR takes over
+            else prec = prec == P32 ? P64 : P32;
             out.inner_used = prec;
             have = true;
             continue;
@@ -970,6 +974,7 @@ struct DenseOut {
     int reliable = 0;
     double true_resid = 0;
     bool converged = false;
+    int inner_used = P64;   // the most precise inner arithmetic used (after escalations)
 };
 
 // Dense hop forms in precision prec: out = ch DA(Dh in) + ca DB(aux) + cr aux2 on output parity par
@@ -1001,8 +1006,8 @@ DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& 
         return out;
     }
     const double bnorm = std::sqrt(b2);
-    const int prec = sp.inner == EOFA_FP32 ? P32 : sp.inner == EOFA_FP16 ? P16 : P64;
-    const bool mixed = prec != P64;
+    int prec = sp.inner == EOFA_FP32 ? P32 : sp.inner == EOFA_FP16 ? P16 : P64;
+    out.inner_used = prec;
     Half& t64 = ws(c, "dn_t", P64);
     Half& bh = ws(c, "dn_bhat", P64);
     Half& s64 = ws(c, "dn_s", P64);
@@ -1010,72 +1015,125 @@ DenseOut solve_dense(eofa_ctx* c, const double* dm, const Half& be, const Half& 
     dense_hop(c, dm, P64, false, 0, nullptr, t64, I5, 1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
     dense_hop(c, dm, P64, false, 1, &t64, bh, I5, -1.0, nullptr, I5, 0.0, &bo, 1.0, nullptr);
     zero(c, xo);
-    Half& t = ws(c, "dn_t", prec);
-    Half& sr = ws(c, "dn_s", prec);   // s = bhat - Mhat x_o (its recursion)
-    Half& r = ws(c, "dn_r", prec);    // r = Mhat^dag s
-    Half& p = ws(c, "dn_p", prec);
-    Half& w = ws(c, "dn_w", prec);
-    Half& xl = mixed ? ws(c, "dn_xlo", P32) : xo;   // where the iterations sum x
-    if (mixed) zero(c, xl);
-    convert(c, bh, sr);
-    auto mhat = [&](const Half& in, Half& o, double* partial) {   // o = Mhat in
-        dense_hop(c, dm, prec, false, 0, &in, t, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
-        dense_hop(c, dm, prec, false, 1, &t, o, I5, -1.0, &in, D5(0), 1.0, nullptr, 0.0, partial);
-    };
-    auto mhat_dag = [&](const Half& in, Half& o, double* partial) {   // o = Mhat^dag in
-        dense_hop(c, dm, prec, true, 0, &in, t, D5Inv(1), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
-        dense_hop(c, dm, prec, true, 1, &t, o, I5, -1.0, &in, D5(1), 1.0, nullptr, 0.0, partial);
-    };
-    auto fold = [&]() {   // x_o += x_lo, x_lo = 0
-        hipchk(launch_accum_hi(P32, xo.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
-    };
     const double target = sp.tol * bnorm;
     const double delta = sp.reliable_delta > 0 ? sp.reliable_delta : 0.1;
-    double rmax = std::sqrt(norm2(c, bh, S_T1));   // true residual at the last reliable update
-    mhat_dag(sr, r, c->partial);
-    reduce(c, nb, S_T0);
-    double gam = read_slot(c, S_T0);
-    check_finite(gam, "dense CG");
-    convert(c, r, p);
-    while (out.iters < sp.maxiter && gam > 0.0) {
-        mhat(p, w, c->partial);
-        reduce(c, nb, S_T0);
-        const double ww = read_slot(c, S_T0);
-        check_finite(ww, "dense CG");
-        if (!(ww > 0.0)) break;
-        const double alpha = gam / ww;
-        // x += alpha p ; s -= alpha w ; |s|^2
-        const int ev = timing_begin(c);
-        hipchk(launch_cg_step(prec, xl.d, p.d, p.nrm, sr.d, sr.nrm, w.d, w.nrm, alpha, c->n5, c->N, c->partial,
-                              c->nblk_blas, c->st),
-               "cg step");
-        timing_end(c, ev, C_BLAS, (double)c->n5 * 6.0 * spinor_bytes(prec));
-        reduce(c, c->nblk_blas, S_T1);
-        ++out.iters;
-        double rn = std::sqrt(read_slot(c, S_T1));
-        check_finite(rn, "dense CG");
-        if (mixed && (rn <= delta * rmax || rn <= target)) {
-            // reliable update: s = bhat - Mhat x in FP64 (Mhat x = D5 x - Dh_oe D5^-1 Dh_eo x)
-            fold();
-            dense_hop(c, dm, P64, false, 0, &xo, t64, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
-            dense_hop(c, dm, P64, false, 1, &t64, s64, I5, 1.0, &xo, D5(0), -1.0, &bh, 1.0, c->partial);
-            reduce(c, nb, S_T1);
-            const double rr = read_slot(c, S_T1);
-            check_finite(rr, "true residual");
-            rmax = rn = std::sqrt(rr);
-            ++out.reliable;
+    // s64 = bhat - Mhat x_o in FP64 (Mhat x = D5 x - Dh_oe D5^-1 Dh_eo x), |s64|^2 in slot S_T1
+    auto true_residual = [&]() -> double {
+        dense_hop(c, dm, P64, false, 0, &xo, t64, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+        dense_hop(c, dm, P64, false, 1, &t64, s64, I5, 1.0, &xo, D5(0), -1.0, &bh, 1.0, c->partial);
+        reduce(c, nb, S_T1);
+        const double rr = read_slot(c, S_T1);
+        check_finite(rr, "true residual");
+        return std::sqrt(rr);
+    };
+    // The CG runs in `prec` from the current x_o.  A 16-bit (then FP32)
+    // solve that stops making progress continues one precision up from its
+    // iterate, as in the Cayley-form solver: the reduced-precision recursion
+    // can stall (lost conjugacy) with its residual estimate above the
+    // reliable-update threshold.
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        const bool mixed = prec != P64;
+        Half& t = ws(c, "dn_t", prec);
+        Half& sr = ws(c, "dn_s", prec);   // s = bhat - Mhat x_o (its recursion)
+        Half& r = ws(c, "dn_r", prec);    // r = Mhat^dag s
+        Half& p = ws(c, "dn_p", prec);
+        Half& w = ws(c, "dn_w", prec);
+        Half& xl = mixed ? ws(c, "dn_xlo", P32) : xo;   // where the iterations sum x
+        auto mhat = [&](const Half& in, Half& o, double* partial) {   // o = Mhat in
+            dense_hop(c, dm, prec, false, 0, &in, t, D5Inv(0), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+            dense_hop(c, dm, prec, false, 1, &t, o, I5, -1.0, &in, D5(0), 1.0, nullptr, 0.0, partial);
+        };
+        auto mhat_dag = [&](const Half& in, Half& o, double* partial) {   // o = Mhat^dag in
+            dense_hop(c, dm, prec, true, 0, &in, t, D5Inv(1), 1.0, nullptr, I5, 0.0, nullptr, 0.0, nullptr);
+            dense_hop(c, dm, prec, true, 1, &t, o, I5, -1.0, &in, D5(1), 1.0, nullptr, 0.0, partial);
+        };
+        auto fold = [&]() {   // x_o += x_lo, x_lo = 0
+            hipchk(launch_accum_hi(P32, xo.d, xl.d, xl.nrm, c->n5, c->N, c->nblk_blas, c->st), "accum");
+        };
+        if (mixed) zero(c, xl);
+        double rmax;   // true residual at the last reliable update
+        if (attempt == 0) {
+            convert(c, bh, sr);
+            rmax = std::sqrt(norm2(c, bh, S_T1));
+        } else {
+            rmax = true_residual();
             convert(c, s64, sr);
         }
-        if (rn <= target) break;
-        mhat_dag(sr, r, c->partial);
-        reduce(c, nb, S_T0);
-        const double g2 = read_slot(c, S_T0);
-        check_finite(g2, "dense CG");
-        // p <- r + (g2 / gam) p
-        dense_hop(c, dm, prec, false, 0, nullptr, p, I5, 1.0, &p, I5, g2 / gam, &r, 1.0, nullptr);
-        gam = g2;
+        if (rmax <= target) break;
+        // p = r = Mhat^dag s
+        auto restart = [&]() -> double {
+            mhat_dag(sr, r, c->partial);
+            reduce(c, nb, S_T0);
+            const double g = read_slot(c, S_T0);
+            check_finite(g, "dense CG");
+            convert(c, r, p);
+            return g;
+        };
+        double gam = restart();
+        // progress guard (mixed only): a segment between reliable updates
+        // longer than max(400, 4 x the longest so far), or 1000 iterations
+        // without halving the true residual, forces a reliable update; if
+        // that confirms the stall, this precision is exhausted
+        int seg_iters = 0, seg_max = 0, it_halve = out.iters;
+        double r_halve = rmax;
+        bool stagnated = false;
+        while (out.iters < sp.maxiter && gam > 0.0) {
+            mhat(p, w, c->partial);
+            reduce(c, nb, S_T0);
+            const double ww = read_slot(c, S_T0);
+            check_finite(ww, "dense CG");
+            if (!(ww > 0.0)) break;
+            const double alpha = gam / ww;
+            // x += alpha p ; s -= alpha w ; |s|^2
+            const int ev = timing_begin(c);
+            hipchk(launch_cg_step(prec, xl.d, p.d, p.nrm, sr.d, sr.nrm, w.d, w.nrm, alpha, c->n5, c->N,
+                                  c->partial, c->nblk_blas, c->st),
+                   "cg step");
+            timing_end(c, ev, C_BLAS, (double)c->n5 * 6.0 * spinor_bytes(prec));
+            reduce(c, c->nblk_blas, S_T1);
+            ++out.iters;
+            ++seg_iters;
+            double rn = std::sqrt(read_slot(c, S_T1));
+            check_finite(rn, "dense CG");
+            const bool stalled = mixed && seg_iters > std::max(400, 4 * seg_max);
+            const bool overdue = mixed && out.iters - it_halve > 1000;
+            if (mixed && (rn <= delta * rmax || rn <= target || stalled || overdue)) {
+                // reliable update: s = bhat - Mhat x in FP64
+                fold();
+                const double rprev = rmax;
+                rmax = rn = true_residual();
+                ++out.reliable;
+                convert(c, s64, sr);
+                seg_max = std::max(seg_max, seg_iters);
+                seg_iters = 0;
+                if (rn <= target) break;
+                if (rmax <= 0.5 * r_halve) {
+                    r_halve = rmax;
+                    it_halve = out.iters;
+                }
+                if ((stalled && rmax > 0.5 * rprev) || out.iters - it_halve > 1000) {
+                    stagnated = true;
+                    break;
+                }
+                if (stalled) {   // lost conjugacy: restart the directions from the true residual
+                    gam = restart();
+                    continue;
+                }
+            }
+            if (rn <= target) break;
+            mhat_dag(sr, r, c->partial);
+            reduce(c, nb, S_T0);
+            const double g2 = read_slot(c, S_T0);
+            check_finite(g2, "dense CG");
+            // p <- r + (g2 / gam) p
+            dense_hop(c, dm, prec, false, 0, nullptr, p, I5, 1.0, &p, I5, g2 / gam, &r, 1.0, nullptr);
+            gam = g2;
+        }
+        if (mixed) fold();
+        if (!stagnated || prec == P64 || out.iters >= sp.maxiter) break;
+        prec = prec == P16 ? P32 : P64;   // continue one precision up from x_o
+        out.inner_used = prec;
     }
-    if (mixed) fold();
     // x_e = D5^-1 (b_e - Dh_eo x_o)
     dense_hop(c, dm, P64, false, 0, &xo, xe, D5Inv(0), -1.0, &be, D5Inv(0), 1.0, nullptr, 0.0, nullptr);
     // true residual of the full system: b_p - D5 x_p - Dh x_pbar
@@ -1123,7 +1181,7 @@ int solve_dense_impl(eofa_ctx* c, double m1, double m2, const void* phi, void* c
             stats->iters[sys] = o.iters;
             stats->reliable_updates[sys] = o.reliable;
             stats->true_resid[sys] = o.true_resid;
-            stats->inner_used[sys] = sp->inner;
+            stats->inner_used[sys] = (eofa_prec_t)o.inner_used;
         }
         if (!o.converged) status = EOFA_ENOCONV;
     }
@@ -1513,25 +1571,27 @@ void free_ctx(eofa_ctx* c) {
 
 // Cache-blocked traversal of the hopping kernel.  XCD x (of 8) runs one
 // contiguous range of logical blocks (see xcd_block), so the site table is
-// laid out as 8 regions: the lattice is cut into 8 slabs along `split`, one
-// per XCD.  Inside a slab the sites are visited tile by tile; a tile spans
-// the whole x extent and `ty`, `tz`, `tt` along y, z, t (clamped to the
-// slab), except along `sweep`, which the tile walks one slice at a time.
-// Every slice then needs the slices before and after it along `sweep`,
-// which are still in that XCD's L2, and only the tile's faces across the
-// other directions are read again by the neighbouring tile.  Rows of x hold
-// consecutive checkerboard indices, so the table is the same for both
-// parities.  The sweep may be cut into chunks of ext[sweep] slices.
-// Returns the natural order if the split does not divide.
-struct Tiling { int split, sweep, ext[3]; };   // dims 1 = y, 2 = z, 3 = t
+// laid out as 8 regions, one per XCD: the lattice is cut into parts[d]
+// pieces along y, z and t (their product is 8).  Inside a region the sites
+// are visited tile by tile; a tile spans the whole x extent and `ty`, `tz`,
+// `tt` along y, z, t (clamped to the region), except along `sweep`, which
+// the tile walks one slice at a time.  Every slice then needs the slices
+// before and after it along `sweep`, which are still in that XCD's L2, and
+// only the tile's faces across the other directions are read again by the
+// neighbouring tile.  Rows of x hold consecutive checkerboard indices, so
+// the table is the same for both parities.  The sweep may be cut into
+// chunks of ext[sweep] slices.  Returns the natural order if the parts do
+// not divide the extents.
+struct Tiling { int parts[4], sweep, ext[3]; };   // dims 1 = y, 2 = z, 3 = t; parts[0] unused
 
 std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
     const int Vh = c->Vh, NS = c->NS, nslot = c->nblk_hop * NS;
     std::vector<int> ord;
     ord.reserve(nslot);
     const int hx = c->L[0] / 2;   // checkerboard sites per x row
-    const bool ok = T.split >= 1 && T.split <= 3 && T.sweep >= 1 && T.sweep <= 3 && c->L[T.split] % 8 == 0 &&
-                    (c->L[0] % 2 == 0);
+    bool ok = T.sweep >= 1 && T.sweep <= 3 && (c->L[0] % 2 == 0) &&
+              T.parts[1] * T.parts[2] * T.parts[3] == 8;
+    for (int d = 1; d < 4 && ok; ++d) ok = T.parts[d] >= 1 && c->L[d] % T.parts[d] == 0;
     if (ok) {
         int lo[4] = {0, 0, 0, 0}, hi[4] = {c->L[0], c->L[1], c->L[2], c->L[3]};
         int ext[4] = {c->L[0], T.ext[0], T.ext[1], T.ext[2]};
@@ -1539,10 +1599,15 @@ std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
         int od[2], k = 0;   // the two non-sweep dims among y, z, t, slower one first
         for (int d = 3; d >= 1; --d) if (d != T.sweep) od[k++] = d;
         for (int X = 0; X < 8; ++X) {
-            lo[T.split] = X * (c->L[T.split] / 8);
-            hi[T.split] = lo[T.split] + c->L[T.split] / 8;
+            int r = X;
+            for (int d = 1; d < 4; ++d) {   // region of XCD X, y fastest
+                const int w = c->L[d] / T.parts[d], i = r % T.parts[d];
+                r /= T.parts[d];
+                lo[d] = i * w;
+                hi[d] = lo[d] + w;
+            }
             // the sweep runs in chunks of ext[sweep] slices (all tiles of the
-            // slab visit one chunk before the next); <= 1 means one chunk
+            // region visit one chunk before the next); <= 1 means one chunk
             const int cw = ext[T.sweep] > 1 ? ext[T.sweep] : hi[T.sweep] - lo[T.sweep];
             for (int c0 = lo[T.sweep]; c0 < hi[T.sweep]; c0 += cw)
             for (int a0 = lo[od[0]]; a0 < hi[od[0]]; a0 += ext[od[0]])
@@ -1576,23 +1641,29 @@ std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
 }
 
 // Default tiling per precision (measured at 24^3x64, Ls = 24, and in a
-// model of the per-XCD L2): slabs along z, tiles of 4 (FP16) or 8 (other
-// precisions) y rows by the slab's z planes, walked along t.  The tuning
-// override EOFA_TILE="split,ty,tz,tt,sweep" with dims given as y, z or t
-// replaces it (e.g. "z,4,3,1,t").
+// model of the per-XCD L2): 8 slabs along z, tiles of 4 (FP16) or 8 (other
+// precisions) y rows by the slab's z planes, walked along t.  Tuning
+// overrides (dims given as y, z or t):
+//   EOFA_TILE="split,ty,tz,tt,sweep"          8 slabs along `split` (e.g. "z,4,3,1,t")
+//   EOFA_TILE="p<py>,<pz>,<pt>,ty,tz,tt,sweep" py x pz x pt regions (e.g. "p1,2,4,6,12,1,t")
+//   EOFA_TILE="none"                          natural order
 Tiling default_tiling(const eofa_ctx* c, int prec) {
-    Tiling T{0, 3, {prec == P16 ? 4 : 8, 1, 1}};
-    if (c->L[2] % 8 == 0) { T.split = 2; T.ext[1] = c->L[2] / 8; }
-    else if (c->L[3] % 8 == 0) { T.split = 3; T.sweep = 3; T.ext[0] = 6; T.ext[1] = 4; }
-    else if (c->L[1] % 8 == 0) { T.split = 1; T.ext[0] = c->L[1] / 8; T.ext[1] = c->L[2]; }
+    Tiling T{{1, 1, 1, 1}, 3, {prec == P16 ? 4 : 8, 1, 1}};
+    if (c->L[2] % 8 == 0) { T.parts[2] = 8; T.ext[1] = c->L[2] / 8; }
+    else if (c->L[3] % 8 == 0) { T.parts[3] = 8; T.ext[0] = 6; T.ext[1] = 4; }
+    else if (c->L[1] % 8 == 0) { T.parts[1] = 8; T.ext[0] = c->L[1] / 8; T.ext[1] = c->L[2]; }
+    else T.sweep = 0;   // natural order
     if (const char* e = getenv("EOFA_TILE")) {
+        auto dim = [](char ch) { return ch == 'y' ? 1 : ch == 'z' ? 2 : ch == 't' ? 3 : 0; };
         char sp = 0, sw = 0;
-        int ty = 0, tz = 0, tt = 0;
-        if (sscanf(e, "%c,%d,%d,%d,%c", &sp, &ty, &tz, &tt, &sw) == 5) {
-            auto dim = [](char ch) { return ch == 'y' ? 1 : ch == 'z' ? 2 : ch == 't' ? 3 : 0; };
-            T = Tiling{dim(sp), dim(sw), {ty, tz, tt}};
+        int py = 0, pz = 0, pt = 0, ty = 0, tz = 0, tt = 0;
+        if (sscanf(e, "p%d,%d,%d,%d,%d,%d,%c", &py, &pz, &pt, &ty, &tz, &tt, &sw) == 7) {
+            T = Tiling{{1, py, pz, pt}, dim(sw), {ty, tz, tt}};
+        } else if (sscanf(e, "%c,%d,%d,%d,%c", &sp, &ty, &tz, &tt, &sw) == 5) {
+            T = Tiling{{1, 1, 1, 1}, dim(sw), {ty, tz, tt}};
+            if (dim(sp)) T.parts[dim(sp)] = 8;
         } else if (strcmp(e, "none") == 0) {
-            T.split = 0;
+            T.sweep = 0;
         }
     }
     return T;

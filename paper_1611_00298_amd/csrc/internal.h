@@ -279,7 +279,7 @@ struct HopArgs {
     // dsc[s_num] / dsc[s_den], which is also stored to dsc[s_alpha] (>= 0)
     double* dsc;
     int s_num, s_den, s_alpha;
-    // dense 5D blocks of D_EOFA's even-odd form (FP64 comparison path only):
+    // dense 5D blocks of D_EOFA's even-odd form (the dense comparison path, FP64, FP32 or FP16):
     // [D5+, D5-, D5inv+, D5inv-], each Ls x Ls row major; an Op5 of kind 3
     // applies D5 (a = 0) or D5^-1 (a = 1), transposed when tr != 0
     const double* dmat;

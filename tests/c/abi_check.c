@@ -148,7 +148,7 @@ int main(void) {
 
     /* 2. EOFA solves with the FP16 inner solver, and the action */
     const double m1 = 0.04, m2 = 1.0;
-    eofa_solver_t sp = {1e-10, 20000, EOFA_FP16, 0.3};
+    eofa_solver_t sp = {1e-10, 20000, EOFA_FP16, 0.3, 0};
     eofa_stats_t st;
     double S = 0;
     rc = eofa_solve(ctx, m1, m2, dphi, NULL, NULL, dchiL, dchiR, NULL, &S, &sp, &st);
@@ -186,7 +186,7 @@ int main(void) {
         CHECK(rc == EOFA_OK && Sg > 0.0 && isfinite(Sg), "gauge action of random links: %d %g", rc, Sg);
 
         /* the dense D_EOFA path (FP32 inner) solves the same systems */
-        eofa_solver_t sp32 = {1e-10, 20000, EOFA_FP32, 0.3};
+        eofa_solver_t sp32 = {1e-10, 20000, EOFA_FP32, 0.3, 0};
         double Sd = 0;
         rc = eofa_solve_dense(ctx, m1, m2, dphi, dchiL, dchiR, NULL, &Sd, &sp32, &st);
         CHECK(rc == EOFA_OK && fabs(Sd - S) <= 1e-9 * fabs(S), "dense solve: %d %.15e vs %.15e", rc, Sd, S);
@@ -208,7 +208,7 @@ int main(void) {
         /* heatbath of eq. (3.1): phi^dag M_EOFA phi = eta^dag eta up to the
          * approximation error on an interval from the Lanczos bounds */
         double th[2], res[2];
-        eofa_solver_t spb = {1e-8, 20000, EOFA_FP64, 0.3};
+        eofa_solver_t spb = {1e-8, 20000, EOFA_FP64, 0.3, 1};
         rc = eofa_meofa_bounds(ctx, m1, m2, dphi, 20, &spb, th, res, NULL);
         CHECK(rc == EOFA_OK && th[0] > 0 && th[1] > th[0], "meofa bounds: %d %g %g", rc, th[0], th[1]);
         double a0, al[8], be[8], delta;

@@ -43,7 +43,7 @@ int main(void) {
     EXPECT(eofa_rational_inv_sqrt(1.0, 2.0, 4, NULL, al, be, &delta) == EOFA_EINVAL, "NULL accepted");
     EXPECT(strlen(eofa_last_error()) > 0, "no error message");
 
-    const eofa_solver_t sp = {1e-10, 100, EOFA_FP64, 0.3};
+    const eofa_solver_t sp = {1e-10, 100, EOFA_FP64, 0.3, 0};
     eofa_stats_t st;
     double S, th[2], r[2];
     EXPECT(dwf_apply(NULL, 0.1, 0.1, 0, 0, EOFA_FP64, NULL, NULL) == EOFA_EINVAL, "dwf_apply");

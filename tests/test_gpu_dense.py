@@ -110,3 +110,24 @@ def test_dense_zero_source_and_errors():
         # maxiter too small: not converged, statistics still written
         _, _, _, _, st = ctx.eofa_solve_dense(phi, 0.1, 0.5, tol=1e-12, maxiter=3, allow_noconv=True)
         assert not st["converged"] and st["iters"] == [3, 3]
+
+
+def test_dense_fp16_progress_guard():
+    """With reliable updates switched off (delta = 1e-30) the FP16 recursion
+    loses track of the true residual; the progress guard still forces FP64
+    residual recomputations, and the solve ends at the requested true
+    residual (in FP16, or after continuing in FP32 or FP64, as reported)."""
+    from paper_1611_00298_amd import Context
+    L, Ls, m1, m2 = C1["L"], C1["Ls"], C1["m1"], C1["m2"]
+    U = din.random_gauge(L, C1["eps"], C1["seed_gauge"])
+    phi = din.gaussian_4d(L, C1["seed_phi"])
+    lat = oracle.Lattice(L, Ls, M5=C1["M5"], alpha=C1["alpha"])
+    with Context(L, Ls, to_dev(U), M5=C1["M5"], alpha=C1["alpha"]) as ctx:
+        chiL, chiR, _, S, st = ctx.eofa_solve_dense(to_dev(phi), m1, m2, tol=1e-10, inner="fp16",
+                                                    reliable_delta=1e-30, maxiter=40000, want_mphi=False)
+    print(f"dense fp16 guard: iters {st['iters']} reliable {st['reliable_updates']} inner {st['inner_used']}")
+    assert st["converged"] and min(st["reliable_updates"]) >= 1
+    assert all(p in ("fp16", "fp32", "fp64") for p in st["inner_used"])
+    vL, vR = sources(lat, phi, m1, m2)
+    assert rel(oracle.H_op(lat, U, m1, m1, chiL.cpu().numpy()), vL) <= 1e-10
+    assert rel(oracle.H_op(lat, U, m1, m2, chiR.cpu().numpy()), vR) <= 1e-10
