@@ -24,7 +24,8 @@ Other modes, each printing its own JSON line instead:
   --trajectory  the 24^3x64 leapfrog trajectory, mixed vs FP64 (dH, reversibility)
   --heatbath    the eq. (3.1) heatbath: Lanczos interval, Zolotarev poles, 2 N_p solves
   --hmc         one full trajectory (heatbath, force-gradient MD, energies) by phase;
-                --gauge-beta adds the Iwasaki gauge action on an inner time scale
+                --gauge-beta adds the Iwasaki gauge action on an inner time scale;
+                --trajectories N runs a chain with M_EOFA's interval reused
   --gauge       the gauge force and action kernels (Iwasaki and Wilson)
   --dense       the EOFA solves on D_EOFA itself against the Cayley form (Table 4)
 """
@@ -634,6 +635,69 @@ def hmc(args):
     return 0
 
 
+def hmc_chain(args):
+    """args.trajectories EOFA HMC trajectories in a chain (run_chain) on the
+    24^3x64, Ls = 24 trajectory workload, force-gradient integration as in
+    --hmc, with M_EOFA's interval estimated by Lanczos before the first
+    trajectory and reused for args.interval_every trajectories (checked
+    after every heatbath by phi^dag M phi = eta^dag eta).  Reports the
+    Lanczos time amortised over the chain.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import dwf_inputs as din
+    from paper_1611_00298_amd import IWASAKI_C1, Context
+    from paper_1611_00298_amd.hmc import force_gradient, run_chain
+
+    pre = din.preset("c5")
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    m1, m2 = pre["m1"], pre["m2"]
+    n, dt = args.md_steps, 1.0 / args.md_steps
+    log("hmc chain: generating c5 inputs")
+    U = t(din.random_gauge(pre["L"], pre["eps"], pre["seed_gauge"]))
+    ctx = Context(pre["L"], pre["Ls"], U, M5=pre["M5"], alpha=pre["alpha"])
+    gauge = (args.gauge_beta, IWASAKI_C1) if args.gauge_beta > 0 else None
+
+    def draw(rng):
+        # per-trajectory seeds for the seeded generators of dwf_inputs
+        se, sp = (int(v) for v in rng.integers(1, 2**31, size=2))
+        return t(din.gaussian_4d(pre["L"], se)), t(din.gaussian_momenta(pre["L"], sp)), float(rng.random())
+
+    timings = []
+    prog = lambda i, st: log(f"hmc chain: force {i}: iters {st['iters']} solve {st['seconds']:.2f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = run_chain(ctx, U, args.trajectories, draw, np.random.Generator(np.random.PCG64(pre["seed_mom"])),
+                     m1, m2, n, dt, interval=dict(refresh_every=args.interval_every, n_iter=args.lanczos,
+                                                  tol=args.lanczos_tol, guard=1e-6),
+                     timings=timings, integrator=force_gradient, progress=prog, chrono=args.chrono,
+                     gauge=gauge, n_gauge=args.n_gauge, tol=1e-10, inner=args.inner,
+                     reliable_delta=args.delta)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ctx.close()
+    t_int = sum(x["interval_s"] for x in timings)
+    for i, (r, x) in enumerate(zip(recs, timings)):
+        log(f"hmc chain: trajectory {i}: interval {x['interval_s']:.1f} s, trajectory {x['trajectory_s']:.1f} s, "
+            f"dH {r['dH']:.4f}, accepted {r['accepted']}")
+    out = {"metric": "EOFA HMC chain: time per trajectory with the M_EOFA interval reused (1 GPU)",
+           "value": total / len(recs), "unit": "s per trajectory", "higher_is_better": False,
+           "config": {"workload": f"EOFA Moebius DWF {'x'.join(map(str, pre['L']))}, Ls={pre['Ls']}, "
+                                  f"alpha={pre['alpha']}, M5={pre['M5']}, m1={m1}, m2={m2}: {len(recs)} "
+                                  f"trajectories of {n} force-gradient steps, tau = 1, solves to 1e-10",
+                      "inner_precision": args.inner, "interval_every": args.interval_every,
+                      "gauge": None if gauge is None else {"beta": gauge[0], "c1": gauge[1]}},
+           "data": "synthetic (random SU(3) links exp(i eps H); Gaussian eta and momenta per trajectory)",
+           "interval_lanczos_s_total": t_int, "interval_share": t_int / total,
+           "interval_s_per_trajectory": t_int / len(recs),
+           "trajectories": [{"interval_s": x["interval_s"], "trajectory_s": x["trajectory_s"], "dH": r["dH"],
+                             "accepted": r["accepted"], "interval": r["interval"],
+                             "heatbath_iters": r["heatbath_iters"], "md_iters": r["md_iters"]}
+                            for r, x in zip(recs, timings)]}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -660,6 +724,10 @@ def main():
                     help="instead of the step benchmark: one full EOFA HMC trajectory (heatbath, force-gradient "
                          "integration, energies) on the 24^3x64 trajectory workload, timed by phase")
     ap.add_argument("--md-steps", type=int, default=12, help="hmc: force-gradient steps per unit trajectory")
+    ap.add_argument("--trajectories", type=int, default=1,
+                    help="hmc: run a chain of this many trajectories with the M_EOFA interval reused")
+    ap.add_argument("--interval-every", type=int, default=4,
+                    help="hmc chain: trajectories between Lanczos estimates of M_EOFA's interval")
     ap.add_argument("--gauge-beta", type=float, default=0.0,
                     help="hmc: add the Iwasaki gauge action at this beta (0: fermion-only; Table 1's 24ID: 1.633)")
     ap.add_argument("--n-gauge", type=int, default=2,
@@ -688,7 +756,7 @@ def main():
     if args.heatbath:
         return heatbath(args)
     if args.hmc:
-        return hmc(args)
+        return hmc_chain(args) if args.trajectories > 1 else hmc(args)
     if args.dslash:
         return dslash(args)
     if args.gauge:

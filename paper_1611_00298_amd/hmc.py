@@ -166,9 +166,14 @@ def force_gradient(ctx: Context, U, P, phi, m1, m2, n_steps, dt, progress=None, 
     return fs.stats
 
 
+class HeatbathIntervalError(RuntimeError):
+    """phi^dag M_EOFA phi missed eta^dag eta by more than the guard: the
+    rational approximation's interval no longer holds M_EOFA's spectrum."""
+
+
 def trajectory(ctx: Context, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_accept=None,
                integrator=None, progress=None, chrono=0, gauge=None, n_gauge=0,
-               gauge_scheme="force_gradient", **solver):
+               gauge_scheme="force_gradient", heatbath_guard=None, **solver):
     """One HMC trajectory from links U and fresh momenta P (both updated in
     place; restored on rejection):
     phi = M_EOFA^(-1/2) eta (eq. (3.1), Zolotarev on [lo, hi] with n_poles),
@@ -177,13 +182,24 @@ def trajectory(ctx: Context, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_
     when u_accept is None).  chrono > 0 starts the molecular-dynamics solves
     from chronological guesses over the last `chrono` solutions (history
     cleared here, since phi is new).  gauge = (beta, c1), n_gauge and
-    gauge_scheme add the gauge action (module docstring).  Returns a dict with H0, dH, accepted,
-    the fermion and gauge actions and the heatbath and force statistics."""
+    gauge_scheme add the gauge action (module docstring).  heatbath_guard:
+    if given, phi^dag M_EOFA phi = S0 must equal eta^dag eta to this
+    relative tolerance (up to the approximation error, the heatbath draws
+    phi with exactly that weight), else HeatbathIntervalError is raised
+    before any molecular dynamics, with U and P untouched.  Returns a dict
+    with H0, dH, accepted, the fermion and gauge actions and the heatbath
+    and force statistics."""
     ctx.update_gauge(U)
     phi, hb = ctx.eofa_heatbath(eta, m1, m2, lo=lo, hi=hi, n_poles=n_poles, **solver)
     ctx.chrono(chrono)
     U0, P0 = U.clone(), P.clone()
     H0, S0, K0, _ = hamiltonian(ctx, U, P, phi, m1, m2, gauge=gauge, **solver)
+    if heatbath_guard is not None:
+        import torch
+        ee = float(torch.linalg.vecdot(eta.reshape(-1), eta.reshape(-1)).real)
+        if abs(S0 / ee - 1.0) > heatbath_guard:
+            raise HeatbathIntervalError(f"phi^dag M phi / eta^dag eta - 1 = {S0 / ee - 1.0:.3e} "
+                                        f"exceeds {heatbath_guard:.1e} on [{lo}, {hi}]")
     step = integrator or leapfrog
     st = step(ctx, U, P, phi, m1, m2, n_steps, dt, progress=progress, gauge=gauge, n_gauge=n_gauge,
               gauge_scheme=gauge_scheme, **solver)
@@ -207,9 +223,10 @@ def _ckpt_paths(d):
     return os.path.join(d, "links.npy"), os.path.join(d, "state.json")
 
 
-def save_checkpoint(directory, U, rng, records):
-    """Write the links, the generator's state and the trajectory records to
-    `directory` (each file replaced atomically, the state file last)."""
+def save_checkpoint(directory, U, rng, records, interval=None):
+    """Write the links, the generator's state, the trajectory records and
+    the heatbath interval in use (if any) to `directory` (each file
+    replaced atomically, the state file last)."""
     import json
     import os
 
@@ -219,15 +236,16 @@ def save_checkpoint(directory, U, rng, records):
     tmp = links + ".tmp.npy"
     np.save(tmp, U.detach().cpu().numpy())
     os.replace(tmp, links)
-    doc = {"n_done": len(records), "rng": rng.bit_generator.state, "records": records}
+    doc = {"n_done": len(records), "rng": rng.bit_generator.state, "records": records, "interval": interval}
     with open(state + ".tmp", "w") as fh:
         json.dump(doc, fh)
     os.replace(state + ".tmp", state)
 
 
-def load_checkpoint(directory, U, rng):
+def load_checkpoint(directory, U, rng, with_interval=False):
     """Restore a checkpoint written by save_checkpoint into U (in place) and
-    rng; returns the trajectory records, or None if there is none."""
+    rng; returns the trajectory records, or None if there is none (with
+    with_interval: (records, interval) or None)."""
     import json
     import os
 
@@ -248,32 +266,90 @@ def load_checkpoint(directory, U, rng):
     records = doc["records"]
     if len(records) != doc["n_done"]:
         raise ValueError("inconsistent checkpoint")
+    if with_interval:
+        return records, doc.get("interval")
     return records
 
 
-def run_chain(ctx: Context, U, n_traj, draw, rng, m1, m2, n_steps, dt, lo, hi, n_poles, checkpoint=None,
-              **kw):
+def spectral_interval(ctx: Context, start, m1, m2, n_iter=12, tol=1e-5, margin=0.02, delta=1e-10,
+                      **solver):
+    """M_EOFA's spectral interval for the heatbath (Section 3.2): Lanczos
+    extremes (eofa_meofa_bounds, n_iter steps from `start`, solves to tol)
+    widened by their residual bounds and by `margin`, and the fewest
+    Zolotarev poles whose relative error on it is below `delta`.
+    Returns {"lo", "hi", "n_poles", "delta"}."""
+    from .api import rational_inv_sqrt
+    tmin, tmax, rmin, rmax, _ = ctx.meofa_bounds(start, m1, m2, n_iter=n_iter, tol=tol, **solver)
+    lo = (1.0 - margin) * max(tmin - rmin, 0.5 * tmin)
+    hi = (1.0 + margin) * (tmax + rmax)
+    n = next(k for k in range(1, 65) if rational_inv_sqrt(lo, hi, k)[3] <= delta)
+    return {"lo": lo, "hi": hi, "n_poles": n, "delta": rational_inv_sqrt(lo, hi, n)[3]}
+
+
+def run_chain(ctx: Context, U, n_traj, draw, rng, m1, m2, n_steps, dt, lo=None, hi=None, n_poles=None,
+              checkpoint=None, interval=None, timings=None, **kw):
     """Run the chain up to n_traj trajectories from links U (updated in
     place).  draw(rng) -> (eta, P, u) gives each trajectory's heatbath noise,
     momenta and Metropolis uniform (the caller decides how); rng is a
     numpy Generator.  Every other argument goes to trajectory().  With
-    checkpoint (a directory) the links, rng's state and the records are
-    saved after every trajectory, and an existing checkpoint is resumed
-    first, so a stopped chain continues exactly as if it had not stopped.
+    checkpoint (a directory) the links, rng's state, the records and the
+    heatbath interval are saved after every trajectory, and an existing
+    checkpoint is resumed first, so a stopped chain continues exactly as if
+    it had not stopped.
+
+    The heatbath interval is either fixed (lo, hi, n_poles) or, with
+    interval = dict(refresh_every=N, guard=g, **spectral_interval options),
+    estimated by Lanczos before the first trajectory and reused for N
+    trajectories before it is estimated again (M_EOFA's spectrum is narrow
+    and moves little between trajectories, Section 3.2).  Every trajectory
+    then checks phi^dag M_EOFA phi against eta^dag eta to the relative
+    tolerance g (default 1e-6); if that fails, the interval is estimated
+    afresh from the current links and the trajectory is repeated with the
+    same draws.  timings (a list), if given, receives per trajectory the
+    seconds spent on the interval and on the trajectory itself.
     Returns one record per trajectory (dH, acceptance, actions, iterations)."""
-    records = []
+    import time
+    records, iv = [], None
     if checkpoint is not None:
-        got = load_checkpoint(checkpoint, U, rng)
+        got = load_checkpoint(checkpoint, U, rng, with_interval=True)
         if got is not None:
-            records = got
+            records, iv = got
+    if interval is None:
+        if lo is None or hi is None or n_poles is None:
+            raise ValueError("give lo, hi and n_poles, or interval=dict(refresh_every=...)")
+        iv = {"lo": lo, "hi": hi, "n_poles": n_poles, "since": 0}
+    opts = dict(interval or {})
+    every = int(opts.pop("refresh_every", 1))
+    guard = opts.pop("guard", 1e-6) if interval is not None else None
+    solver = {k: kw[k] for k in ("tol", "maxiter", "inner", "reliable_delta") if k in kw}
+    solver.pop("tol", None)
     while len(records) < n_traj:
         eta, P, u = draw(rng)
-        r = trajectory(ctx, U, P, eta, m1, m2, n_steps, dt, lo, hi, n_poles, u_accept=u, **kw)
+        t_iv = 0.0
+        for attempt in range(2):
+            if interval is not None and (iv is None or iv["since"] >= every or attempt > 0):
+                t0 = time.perf_counter()
+                ctx.update_gauge(U)
+                iv = dict(spectral_interval(ctx, eta, m1, m2, **opts, **solver), since=0)
+                t_iv += time.perf_counter() - t0
+            t0 = time.perf_counter()
+            try:
+                r = trajectory(ctx, U, P, eta, m1, m2, n_steps, dt, iv["lo"], iv["hi"], iv["n_poles"],
+                               u_accept=u, heatbath_guard=guard, **kw)
+                break
+            except HeatbathIntervalError:
+                if attempt > 0 or interval is None:
+                    raise
+        t_traj = time.perf_counter() - t0
+        iv["since"] += 1
         records.append({"dH": r["dH"], "accepted": r["accepted"], "S0": r["S0"], "S1": r["S1"],
                         "Sg0": r["Sg0"], "Sg1": r["Sg1"],
                         "heatbath_iters": list(r["heatbath"]["iters"]),
                         "md_iters": [sum(s["iters"][0] for s in r["forces"]),
-                                     sum(s["iters"][1] for s in r["forces"])]})
+                                     sum(s["iters"][1] for s in r["forces"])],
+                        "interval": [iv["lo"], iv["hi"], iv["n_poles"]]})
+        if timings is not None:
+            timings.append({"interval_s": t_iv, "trajectory_s": t_traj})
         if checkpoint is not None:
-            save_checkpoint(checkpoint, U, rng, records)
+            save_checkpoint(checkpoint, U, rng, records, interval=iv)
     return records

@@ -38,3 +38,15 @@ def test_checkpoint_absent_and_mismatch(tmp_path):
     (tmp_path / "state.json").write_text(json.dumps(doc))
     with pytest.raises(ValueError):
         load_checkpoint(tmp_path, U, rng)
+
+
+def test_checkpoint_keeps_the_heatbath_interval(tmp_path):
+    from paper_1611_00298_amd.hmc import load_checkpoint, save_checkpoint
+    U = torch.zeros((4, 2, 2, 2, 2, 3, 3), dtype=torch.complex128)
+    rng = np.random.Generator(np.random.PCG64(3))
+    iv = {"lo": 0.9, "hi": 3.1, "n_poles": 7, "since": 2}
+    save_checkpoint(tmp_path, U, rng, [{"dH": 0.0}], interval=iv)
+    recs, got = load_checkpoint(tmp_path, U, rng, with_interval=True)
+    assert recs == [{"dH": 0.0}] and got == iv
+    save_checkpoint(tmp_path, U, rng, [])
+    assert load_checkpoint(tmp_path, U, rng, with_interval=True) == ([], None)

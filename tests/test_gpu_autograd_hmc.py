@@ -331,3 +331,50 @@ def test_chain_checkpoint_resume(c1, tmp_path):
     assert np.array_equal(Uc.cpu().numpy(), Ua.cpu().numpy())
     assert len(ra) == 3 and all(abs(r["dH"]) < 1.0 for r in ra)
     ctx.update_gauge(to_dev(U0))
+
+
+def test_chain_reuses_the_heatbath_interval(c1, tmp_path):
+    """run_chain with interval reuse: Lanczos before trajectories 0 and 2
+    (refresh_every = 2), none before 1; a stop after 2 trajectories and a
+    resume end where the uninterrupted chain does, interval included."""
+    from paper_1611_00298_amd.hmc import force_gradient, run_chain
+    lat, U0, phi, ctx = c1
+    draw = _draw_factory(C1["L"])
+    iv = dict(refresh_every=2, n_iter=20, tol=1e-8, guard=1e-6)
+    kw = dict(integrator=force_gradient, tol=1e-10, inner="fp16")
+    args = (C1["m1"], C1["m2"], 2, 0.1)
+    Ua, ta = to_dev(U0), []
+    ra = run_chain(ctx, Ua, 3, draw, np.random.Generator(np.random.PCG64(8)), *args, interval=iv,
+                   timings=ta, checkpoint=str(tmp_path / "a"), **kw)
+    assert [t["interval_s"] > 0 for t in ta] == [True, False, True]
+    assert ra[0]["interval"] == ra[1]["interval"] != ra[2]["interval"]
+    lo, hi, n = ra[0]["interval"]
+    assert 0 < lo < 1.0 < hi and n >= 1
+    Ub = to_dev(U0)
+    run_chain(ctx, Ub, 2, draw, np.random.Generator(np.random.PCG64(8)), *args, interval=iv,
+              checkpoint=str(tmp_path / "b"), **kw)
+    rb = run_chain(ctx, Ub, 3, draw, np.random.Generator(np.random.PCG64(8)), *args, interval=iv,
+                   checkpoint=str(tmp_path / "b"), **kw)
+    assert rb == ra
+    assert np.array_equal(Ub.cpu().numpy(), Ua.cpu().numpy())
+    ctx.update_gauge(to_dev(U0))
+
+
+def test_chain_guard_refreshes_a_wrong_interval(c1, tmp_path):
+    """A resumed chain whose saved interval does not hold M_EOFA's spectrum
+    (here [3, 5]; the spectrum starts near 1) fails the phi^dag M phi check
+    of its next heatbath, re-estimates the interval and carries on."""
+    from paper_1611_00298_amd.hmc import run_chain, save_checkpoint
+    lat, U0, phi, ctx = c1
+    draw = _draw_factory(C1["L"])
+    rng = np.random.Generator(np.random.PCG64(9))
+    U = to_dev(U0)
+    save_checkpoint(str(tmp_path), U, rng, [], interval={"lo": 3.0, "hi": 5.0, "n_poles": 6, "since": 0})
+    t = []
+    r = run_chain(ctx, U, 1, draw, rng, C1["m1"], C1["m2"], 2, 0.1, checkpoint=str(tmp_path), timings=t,
+                  interval=dict(refresh_every=100, n_iter=20, tol=1e-8, guard=1e-6), tol=1e-10)
+    assert t[0]["interval_s"] > 0
+    lo, hi, n = r[0]["interval"]
+    assert lo < 1.0 < hi
+    assert abs(r[0]["S0"]) > 0
+    ctx.update_gauge(to_dev(U0))
