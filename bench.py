@@ -68,8 +68,9 @@ def plaquette(ctx, U):
 
 def measured_traffic(inner, workload):
     """HBM bytes per launch of the hopping kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None if
-    there is none or the kernel sources changed since it was taken."""
+    rocprofv3 summary (read and write requests counted by size, see
+    profile_summary), or None if there is none or the kernel sources changed
+    since it was taken."""
     path = os.path.join(ROOT, "profiles", f"k_hop_{inner}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -85,6 +86,160 @@ def measured_traffic(inner, workload):
         return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+HOP_TEMPLATE = {"fp64": "k_hop<0, {}, true, 0, false>", "fp32": "k_hop<1, {}, true, 0, false>",
+                "fp16": "k_hop<2, {}, true, 3, false>", "bf16": "k_hop<3, {}, true, 3, false>"}
+
+
+def profile_summary(args):
+    """Summarise rocprofv3 --pmc runs of this benchmark (default mode) per
+    launch of the hopping kernel, split into its four forms by position: in
+    the CG iteration the hop runs as K1, K2 (not daggered) then K3, K4
+    (daggered), so in the dispatch sequence each run of same-direction hop
+    launches pairs up as (K1, K2) or (K3, K4).  Read bytes are counted from
+    the L2-to-memory read requests by size (128, 64, 32 bytes) and write
+    bytes from the write requests (64 or 32 bytes); the elementwise kernel of
+    --copy-calibration (2 GiB read, 2 GiB written) checks the counting.
+    Prints a text summary for profiles/."""
+    import csv
+    import glob
+    import collections
+    import dwf_inputs as din
+    pre = din.preset(args.workload)
+    Lx, Ly, Lz, Lt = pre["L"]
+    Vh = Lx * Ly * Lz * Lt // 2
+    n5 = Vh * pre["Ls"]
+    sb = {"fp64": 192, "fp32": 96, "fp16": 52, "bf16": 48}[args.inner]
+    cb = {"fp64": 16, "fp32": 8, "fp16": 4, "bf16": 4}[args.inner]
+    links = 72.0 * cb * Vh
+    alg = {"K1": 2 * sb * n5 + links, "K2": 3 * sb * n5 + links, "K3": 2 * sb * n5 + links,
+           "K4": 4 * sb * n5 + links}
+    hop = {HOP_TEMPLATE[args.inner].format("false"): False, HOP_TEMPLATE[args.inner].format("true"): True}
+    disp = collections.defaultdict(dict)   # dispatch id -> counters
+    name = {}
+    for d in args.profile_summary:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                key = (f, int(r["Dispatch_Id"]))
+                disp[key][r["Counter_Name"]] = float(r["Counter_Value"])
+                name[key] = r["Kernel_Name"]
+        # kernel traces: the duration of each dispatch as a pseudo-counter
+        for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                key = (f, int(r["Dispatch_Id"]))
+                disp[key]["duration_us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                name[key] = r["Kernel_Name"]
+    cls = collections.defaultdict(lambda: collections.defaultdict(list))
+    calib = collections.defaultdict(list)
+    for f in sorted({k[0] for k in disp}):
+        keys = sorted(k for k in disp if k[0] == f)
+        run, prev = [], None
+        for k in keys:
+            kn = name[k]
+            if "elementwise" in kn:
+                calib["all"].append(disp[k])
+                continue
+            tmpl = next((t for t in hop if t in kn), None)
+            if tmpl is None:
+                continue
+            dag = hop[tmpl]
+            if prev is not None and dag != prev:
+                run = []
+            run.append(k)
+            if len(run) == 2:
+                for pos, kk in enumerate(run):
+                    c = ("K3", "K4")[pos] if dag else ("K1", "K2")[pos]
+                    for cn, v in disp[kk].items():
+                        cls[c][cn].append(v)
+                run = []
+            prev = dag
+    def rd(c):
+        return 128 * c.get("TCC_EA0_RDREQ_128B_sum", 0) + 64 * c.get("TCC_EA0_RDREQ_64B_sum", 0) + \
+            32 * c.get("TCC_EA0_RDREQ_32B_sum", 0)
+    def wr(c):
+        return 64 * c.get("TCC_EA0_WRREQ_64B_sum", 0) + 32 * (c.get("TCC_EA0_WRREQ_sum", 0) -
+                                                              c.get("TCC_EA0_WRREQ_64B_sum", 0))
+    avg = lambda xs: sum(xs) / len(xs) if xs else float("nan")
+    lines = [f"# {HOP_TEMPLATE[args.inner].format('*')} (the {args.inner} hopping kernel), bench.py, "
+             f"{Lx}x{Ly}x{Lz}x{Lt}, Ls={pre['Ls']}, per launch",
+             "# read bytes = 128 TCC_EA0_RDREQ_128B + 64 TCC_EA0_RDREQ_64B + 32 TCC_EA0_RDREQ_32B;",
+             "# write bytes = 64 TCC_EA0_WRREQ_64B + 32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B)  (no calibration factor)"]
+    cal_r = [rd(c) for c in calib["all"] if "TCC_EA0_RDREQ_128B_sum" in c and rd(c) > 1e9]
+    cal_w = [wr(c) for c in calib["all"] if "TCC_EA0_WRREQ_sum" in c and wr(c) > 1e9]
+    if cal_r or cal_w:
+        lines.append("# check on the 2 GiB elementwise kernels of --copy-calibration: read " +
+                     ", ".join(f"{v / 2**30:.3f}" for v in cal_r[:6]) + " GiB; written " +
+                     ", ".join(f"{v / 2**30:.3f}" for v in cal_w[:6]) + " GiB")
+    tot_n = tot_r = tot_w = tot_a = 0.0
+    rows = []
+    for c in ("K1", "K2", "K3", "K4"):
+        cs = cls[c]
+        if not cs:
+            continue
+        n = max(len(v) for v in cs.values())
+        m = {cn: avg(v) for cn, v in cs.items()}
+        have_rd = "TCC_EA0_RDREQ_128B_sum" in m
+        have_wr = "TCC_EA0_WRREQ_sum" in m
+        r_, w_ = rd(m), wr(m)
+        rows.append((c, n, m, r_ if have_rd else None, w_ if have_wr else None))
+        if have_rd and have_wr:
+            tot_n += n
+            tot_r += n * r_
+            tot_w += n * w_
+            tot_a += n * alg[c]
+    lines.append("kernel_source_sha256: " + kernel_source_hash())
+    if tot_n:
+        lines += [f"launches: {int(tot_n)}", f"fetch_bytes_per_launch: {tot_r / tot_n:.0f}",
+                  f"write_bytes_per_launch: {tot_w / tot_n:.0f}",
+                  f"algorithmic_bytes_per_launch: {tot_a / tot_n:.0f}",
+                  f"measured_over_algorithmic: {(tot_r + tot_w) / tot_a:.3f}"]
+    durs = [(n, m["duration_us"]) for c, n, m, r_, w_ in rows if "duration_us" in m]
+    if durs:
+        nd = sum(n for n, _ in durs)
+        avg_us = sum(n * d for n, d in durs) / nd
+        a_avg = sum(n * alg[c] for c, n, m, r_, w_ in rows if "duration_us" in m) / nd
+        lines.append(f"trace: {int(nd)} launches, average {avg_us:.1f} us, algorithmic {a_avg / 1e9:.3f} GB "
+                     f"per launch: {a_avg / (avg_us * 1e-6) / 1e9:.0f} GB/s = "
+                     f"{a_avg / (avg_us * 1e-6) / 8e12:.3f} of 8 TB/s")
+    for c, n, m, r_, w_ in rows:
+        a_read = alg[c] - sb * n5
+        txt = f"{c}: launches {n}, algorithmic {alg[c] / 1e9:.3f} GB (reads {a_read / 1e9:.3f})"
+        if "duration_us" in m:
+            txt += f", {m['duration_us']:.1f} us ({alg[c] / (m['duration_us'] * 1e-6) / 1e9:.0f} GB/s)"
+        if r_ is not None:
+            txt += f", read {r_ / 1e9:.3f} GB ({r_ / a_read:.2f}x)"
+        if w_ is not None:
+            txt += f", written {w_ / 1e9:.3f} GB ({w_ / (sb * n5):.2f}x)"
+        w = m.get("SQ_WAVES")
+        if w:
+            parts = [f"{k.replace('SQ_INSTS_', '')} {m[k] / w:.0f}" for k in
+                     ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_LDS",
+                      "SQ_INSTS_SALU") if k in m]
+            txt += "; instructions per wave: " + ", ".join(parts)
+        if "SQ_WAVE_CYCLES" in m and "SQ_WAIT_ANY" in m:
+            txt += f"; waves waiting {m['SQ_WAIT_ANY'] / m['SQ_WAVE_CYCLES']:.0%} of their cycles"
+            if "SQ_WAIT_INST_ANY" in m:
+                txt += f" (on dependencies {m['SQ_WAIT_INST_ANY'] / m['SQ_WAVE_CYCLES']:.0%})"
+        if "SQ_LDS_BANK_CONFLICT" in m and "SQ_INSTS_LDS" in m and w:
+            txt += f"; LDS bank-conflict cycles per LDS instruction {m['SQ_LDS_BANK_CONFLICT'] / max(m['SQ_INSTS_LDS'], 1):.2f}"
+        g = m.get("GRBM_GUI_ACTIVE")
+        if g:
+            cyc = g / 8.0   # summed over the 8 XCDs
+            for k, lab in (("TA_TA_BUSY_sum", "TA busy"), ("TD_TD_BUSY_sum", "TD busy"),
+                           ("TD_TC_STALL_sum", "TD stalled on L1"),
+                           ("TCP_PENDING_STALL_CYCLES_sum", "L1 stalled on pending L2 data")):
+                if k in m:
+                    txt += f"; {lab} {m[k] / (256 * cyc):.0%}"
+            if "TCP_TCC_READ_REQ_LATENCY_sum" in m and "TCP_TCC_READ_REQ_sum" in m:
+                txt += (f"; L2 read latency {m['TCP_TCC_READ_REQ_LATENCY_sum'] / m['TCP_TCC_READ_REQ_sum']:.0f} "
+                        f"cycles with {m['TCP_TCC_READ_REQ_LATENCY_sum'] / (256 * cyc):.0f} reads outstanding per CU"
+                        f" ({m['TCP_TCC_READ_REQ_sum'] * 128 / 1e9:.2f} GB L1->L2)")
+        if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m:
+            txt += f"; L2 hit rate {m['TCC_HIT_sum'] / (m['TCC_HIT_sum'] + m['TCC_MISS_sum']):.0%}"
+        lines.append(txt)
+    print("\n".join(lines))
+    return 0
 
 
 def copy_calibration(dev):
@@ -743,9 +898,14 @@ def main():
                     help="time the Iwasaki and Wilson gauge force and action kernels")
     ap.add_argument("--dslash", action="store_true",
                     help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
+    ap.add_argument("--profile-summary", nargs="+", default=None, metavar="DIR",
+                    help="summarise rocprofv3 --pmc output directories of the default mode per hop form "
+                         "(K1..K4) for --inner and --workload, and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 3 x 2 GiB device copies first (counter calibration under rocprofv3)")
     args = ap.parse_args()
+    if args.profile_summary:
+        return profile_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU only; multi-GPU sharding "
                                    "(4D domain decomposition) is not implemented"}))
