@@ -28,6 +28,7 @@ Other modes, each printing its own JSON line instead:
                 --trajectories N runs a chain with M_EOFA's interval reused
   --gauge       the gauge force and action kernels (Iwasaki and Wilson)
   --dense       the EOFA solves on D_EOFA itself against the Cayley form (Table 4)
+  --cpu-baselines  the CPU oracle's operator rates and solve times per workload beside the GPU's
 """
 from __future__ import annotations
 
@@ -300,6 +301,116 @@ def cpu_baseline(pre, seconds=12.0):
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} x oracle D_DWF on a {Lx}x{Ly}x{Lz}x4 slab, Ls={pre['Ls']} "
                       f"({dt:.1f} s, FP64, OpenMP)"}
+
+
+def cpu_baselines(args):
+    """The CPU oracle on this machine's host cores beside the GPU library, per
+    workload: the D_DWF and Mhat^dag Mhat rates at 4^4x8 (c1), 16^3x32x16
+    (c2) and 24^3x64x24 (c3); the full FP64 EOFA solve of both systems
+    (even-odd CGNR in the Cayley form, to 1e-10) at c1, and at c2 its time
+    estimated from 20 timed oracle iterations, next to the GPU's FP64 and
+    FP16-inner solves of the same systems; and at c3, where a CPU solve
+    would take hours, the oracle's recomputation of the GPU solution's true
+    residual |v - H chi| / |v|.  Flops: 1488 per 5D site
+    for D_DWF and 3024 per odd 5D site for each Mhat.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import dwf_inputs as din
+    import oracle
+    from paper_1611_00298_amd import Context
+    dev = torch.device("cuda:0")
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {"metric": "CPU oracle (FP64, OpenMP) beside the GPU: operator rates and EOFA solve times",
+           "cores": threads, "workloads": {}}
+
+    def rate(fn, flops, min_s=1.0):
+        n, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s:
+                return n * flops / dt / 1e9, dt / n
+
+    for w in ("c1", "c2", "c3"):
+        pre = din.preset(w)
+        L, Ls, m1, m2 = pre["L"], pre["Ls"], pre["m1"], pre["m2"]
+        log(f"cpu baselines: {w} {L} Ls={Ls}")
+        lat = oracle.Lattice(L, Ls, M5=pre["M5"], alpha=pre["alpha"])
+        U = din.random_gauge(L, pre["eps"], pre["seed_gauge"])
+        phi = din.gaussian_4d(L, pre["seed_phi"])
+        psi = din.gaussian_5d(L, Ls, 303)
+        n5 = lat.V * Ls
+        r = {}
+        g, sec = rate(lambda: oracle.ddwf(lat, U, m1, m1, psi), n5 * FLOPS_DDWF)
+        r["oracle_ddwf"] = {"GFLOPs": g, "seconds": sec}
+        odd = (lat.parity_mask() == 1)[None, ..., None, None]
+        po = psi * odd
+        g, sec = rate(lambda: oracle.schur(lat, U, m1, m2, oracle.schur(lat, U, m1, m2, po), dagger=True),
+                      2 * 3024 * n5 / 2)
+        r["oracle_mhat_dag_mhat"] = {"GFLOPs": g, "seconds": sec}
+        del psi, po
+        ctx = Context(L, Ls, torch.from_numpy(U).to(dev), M5=pre["M5"], alpha=pre["alpha"])
+        ph = torch.from_numpy(phi).to(dev)
+        ctx.eofa_solve(ph, m1, m2, tol=1e-10, inner="fp16", want_mphi=False)   # warm-up
+        gpu = {}
+        for inner in ("fp64", "fp16"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chiL, chiR, _, S, st = ctx.eofa_solve(ph, m1, m2, tol=1e-10, inner=inner, want_mphi=False)
+            torch.cuda.synchronize()
+            gpu[inner] = {"seconds": time.perf_counter() - t0, "iters": st["iters"], "S": S,
+                          "true_resid": st["true_resid"]}
+        r["gpu_solve"] = gpu
+        if w == "c1":
+            t0 = time.perf_counter()
+            cL, cR, its = oracle.eofa_chi(lat, U, m1, m2, phi, tol=1e-10)
+            t_orc = time.perf_counter() - t0
+            S_orc, _, _ = oracle.action(lat, m1, m2, phi, cL, cR)
+            r["oracle_solve"] = {"seconds": t_orc, "iters": [int(v) for v in its], "S": S_orc,
+                                 "S_rel_vs_gpu_fp64": abs(S_orc - gpu["fp64"]["S"]) / abs(S_orc),
+                                 "gpu_fp64_speedup": t_orc / gpu["fp64"]["seconds"],
+                                 "gpu_fp16_speedup": t_orc / gpu["fp16"]["seconds"]}
+            log(f"cpu baselines: {w}: oracle solve {t_orc:.1f} s, GPU FP64 {gpu['fp64']['seconds']:.2f} s, "
+                f"FP16 {gpu['fp16']['seconds']:.2f} s")
+        elif w == "c2":
+            # a full CPU solve here takes tens of minutes: time 20 iterations of
+            # the oracle's CGNR (the same iteration as the GPU's FP64 solver)
+            # and scale by the GPU's FP64 iteration count, stated as an estimate
+            om_m, _, _ = oracle.omega_k(lat, m1, m2)
+            v = lat.zeros5()
+            v[..., 2:, :] = om_m[:, None, None, None, None, None, None] * phi[None, ..., 2:, :]
+            b = oracle.g5r5(lat, v)
+            t0 = time.perf_counter()
+            oracle.solve_ddwf_eo(lat, U, m1, m1, b, fixed=20)
+            per_it = (time.perf_counter() - t0) / 20
+            n_it = sum(gpu["fp64"]["iters"])
+            r["oracle_solve_estimate"] = {"seconds_per_iteration": per_it, "iterations": n_it,
+                                          "seconds": per_it * n_it,
+                                          "gpu_fp64_speedup": per_it * n_it / gpu["fp64"]["seconds"],
+                                          "gpu_fp16_speedup": per_it * n_it / gpu["fp16"]["seconds"],
+                                          "how": "20 oracle CGNR iterations timed, times the GPU FP64 "
+                                                 "solve's iteration count (both systems)"}
+            log(f"cpu baselines: {w}: oracle {per_it:.2f} s per iteration, ~{per_it * n_it:.0f} s for "
+                f"{n_it} iterations; GPU FP64 {gpu['fp64']['seconds']:.2f} s, FP16 {gpu['fp16']['seconds']:.2f} s")
+            del v, b
+        else:
+            om_m, _, _ = oracle.omega_k(lat, m1, m2)
+            v = lat.zeros5()
+            v[..., 2:, :] = om_m[:, None, None, None, None, None, None] * phi[None, ..., 2:, :]
+            t0 = time.perf_counter()
+            res = float(np.linalg.norm(oracle.H_op(lat, U, m1, m1, chiL.cpu().numpy()) - v) / np.linalg.norm(v))
+            r["oracle_residual_check"] = {"seconds": time.perf_counter() - t0, "resid_L": res,
+                                          "gpu_resid_L": gpu["fp16"]["true_resid"][0]}
+            del v
+        ctx.close()
+        del ctx, ph
+        torch.cuda.empty_cache()
+        out["workloads"][w] = r
+        log(f"cpu baselines: {w}: D_DWF {r['oracle_ddwf']['GFLOPs']:.1f} GFLOP/s, "
+            f"MhatdagMhat {r['oracle_mhat_dag_mhat']['GFLOPs']:.1f} GFLOP/s")
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def dslash(args):
@@ -898,6 +1009,8 @@ def main():
                     help="time the Iwasaki and Wilson gauge force and action kernels")
     ap.add_argument("--dslash", action="store_true",
                     help="instead of the step benchmark: the hopping kernel's rate in all four precisions")
+    ap.add_argument("--cpu-baselines", action="store_true",
+                    help="the CPU oracle's operator rates and solve times per workload beside the GPU's")
     ap.add_argument("--profile-summary", nargs="+", default=None, metavar="DIR",
                     help="summarise rocprofv3 --pmc output directories of the default mode per hop form "
                          "(K1..K4) for --inner and --workload, and exit")
@@ -919,6 +1032,8 @@ def main():
         return hmc_chain(args) if args.trajectories > 1 else hmc(args)
     if args.dslash:
         return dslash(args)
+    if args.cpu_baselines:
+        return cpu_baselines(args)
     if args.gauge:
         return gauge(args)
     if args.dense:

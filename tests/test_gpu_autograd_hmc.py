@@ -193,6 +193,35 @@ def test_chronological_guesses(c1):
     ctx.update_gauge(to_dev(U0))
 
 
+def test_chronological_md_end_point_by_oracle(c1):
+    """The leapfrog end point with chronological guesses (depth 6) against a
+    CPU replay of the same six steps with the oracle's solves, force (eq.
+    (3.2)) and MD update: the history changes the solves' starting points,
+    not what they converge to."""
+    from paper_1611_00298_amd.hmc import leapfrog
+    lat, U0, phi, ctx = c1
+    m1, m2, n, dt = C1["m1"], C1["m2"], 6, 0.05
+    P0 = din.gaussian_momenta(C1["L"], 309)
+    ctx.update_gauge(to_dev(U0))
+    ctx.chrono(6)
+    U, P = to_dev(U0), to_dev(P0)
+    leapfrog(ctx, U, P, to_dev(phi), m1, m2, n, dt, tol=1e-11)
+    ctx.chrono(0)
+
+    def force(Ux):
+        chiL, chiR, _ = oracle.eofa_chi(lat, Ux, m1, m2, phi, tol=1e-12)
+        return oracle.force(lat, Ux, m1, m2, chiL, chiR, want_grad=False)[0]
+
+    Ur, Pr = oracle.md_update(U0, P0, force(U0), 0.5 * dt, dt)
+    for _ in range(1, n):
+        Ur, Pr = oracle.md_update(Ur, Pr, force(Ur), dt, dt)
+    Ur, Pr = oracle.md_update(Ur, Pr, force(Ur), 0.5 * dt, 0.0)
+    assert np.abs(U.cpu().numpy() - Ur).max() < 1e-8
+    assert np.abs(P.cpu().numpy() - Pr).max() < 1e-8
+    assert np.abs(Ur - U0).max() > 1e-3   # the steps moved the links
+    ctx.update_gauge(to_dev(U0))
+
+
 # 16I's gauge coupling (Table 1) with the Iwasaki coefficient
 GAUGE = (2.13, oracle.IWASAKI_C1)
 

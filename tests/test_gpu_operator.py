@@ -10,7 +10,8 @@ from helpers import PREC_TOL, region_rel, rel, to_dev
 pytestmark = pytest.mark.gpu
 
 # (L, Ls, alpha, antiperiodic): C1 shape, ragged workgroup tails, odd Ls,
-# Shamir and alpha = 4, periodic time
+# Shamir and alpha = 4, periodic time, and the extremes of Ls (1, 2 and the
+# largest the library accepts, 64: 4 sites of 64 slices per workgroup)
 CASES = [
     ((4, 4, 4, 4), 8, 2.0, True),
     ((4, 2, 6, 4), 5, 2.0, True),
@@ -18,6 +19,8 @@ CASES = [
     ((4, 4, 2, 2), 16, 1.0, False),
     ((2, 2, 4, 4), 24, 2.0, True),
     ((6, 2, 2, 2), 1, 2.0, True),
+    ((2, 2, 2, 4), 2, 2.0, True),
+    ((2, 2, 2, 6), 64, 2.0, True),
 ]
 MASSES = [(0.04, 0.04), (0.0362, 1.0)]
 
@@ -91,3 +94,23 @@ def test_force_parity_shapes(setup):
     Fr, Gr = oracle.force(lat, U, m1, m2, chiL, chiR)
     assert np.abs(F.cpu().numpy() - Fr).max() <= 1e-12 * np.abs(Fr).max()
     assert np.abs(G.cpu().numpy() - Gr).max() <= 1e-12 * np.abs(Gr).max()
+
+
+@pytest.mark.parametrize("tile", ["p2,2,2,2,2,1,t", "p1,2,4,4,2,1,t", "p2,4,1,2,1,2,t", "z,2,1,1,t", "p2,2,1,2,2,1,t", "none"])
+def test_traversal_layouts(tile, monkeypatch):
+    """The hop's site traversal (the XCD regions and tiles of EOFA_TILE, a
+    tuning override) only reorders the work: D_DWF and Mhat in FP64 and FP16
+    equal the oracle's under every layout, including a partition into 4
+    regions instead of 8 (which falls back to the natural order)."""
+    from paper_1611_00298_amd import Context
+    L, Ls = (4, 8, 8, 16), 8
+    monkeypatch.setenv("EOFA_TILE", tile)
+    U = din.random_gauge(L, 0.4, 31)
+    psi = din.gaussian_5d(L, Ls, 32)
+    lat = oracle.Lattice(L, Ls, M5=1.8, alpha=2.0)
+    with Context(L, Ls, to_dev(U), M5=1.8, alpha=2.0) as ctx:
+        for prec in ("fp64", "fp16"):
+            out = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, prec=prec).cpu().numpy()
+            assert rel(out, oracle.ddwf(lat, U, 0.04, 1.0, psi)) < PREC_TOL[prec]
+            out = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, dagger=True, eo=True, prec=prec).cpu().numpy()
+            assert rel(out, oracle.schur(lat, U, 0.04, 1.0, psi, dagger=True)) < PREC_TOL[prec]
