@@ -16,6 +16,7 @@
 // M_ee = (4-M5) Dtilde + 1 - L and M_ee^-1, with L or L^T.  Inverses use a
 // weighted Hillis-Steele scan over s in LDS plus a rank-one wrap correction.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -606,13 +607,14 @@ __device__ void col_bidiag(A* col, int Ls, bool down, A a, A b, A m) {
     });
 }
 
+// (a + b S)^-1 applied to xs times the column
 template <int CB, typename A>
-__device__ void col_inverse(A* col, int Ls, bool down, A a, A b, A m) {
+__device__ void col_inverse(A* col, int Ls, bool down, A a, A b, A m, A xs = A(1)) {
     const int s0 = down ? 0 : Ls - 1, ds = down ? 1 : -1;
-    const A ia = A(1) / a, w = -b * ia;
+    const A ia = A(1) / a, w = -b * ia, iax = ia * xs;
     A z = 0;
     col_pass<CB>(col, Ls, s0, ds, [&](A x) {
-        z = fmadd(w, z, ia * x);
+        z = fmadd(w, z, iax * x);
         return z;
     });
     const A K = -m * z / (A(1) + m * ipow(w, Ls));
@@ -621,6 +623,31 @@ __device__ void col_inverse(A* col, int Ls, bool down, A a, A b, A m) {
         const A y = fmadd(K, pw, x);
         pw *= w;
         return y;
+    });
+}
+
+// (a2 + b2 S)^-1 (a1 + b1 S) applied to the column in two passes instead of
+// three: the bidiagonal op and the inverse's forward recursion run in one
+// sweep (both walk the column in the same direction), then the inverse's
+// rank-one wrap correction
+template <int CB, typename A>
+__device__ void col_bidiag_inverse(A* col, int Ls, bool down, A a1, A b1, A a2, A b2, A m) {
+    const int s0 = down ? 0 : Ls - 1, ds = down ? 1 : -1;
+    A prev = -m * col[(s0 + ds * (Ls - 1)) * STR];
+    const A ia = A(1) / a2, w = -b2 * ia;
+    A z = 0;
+    col_pass<CB>(col, Ls, s0, ds, [&](A x) {
+        const A y = fmadd(b1, prev, a1 * x);
+        prev = x;
+        z = fmadd(w, z, ia * y);
+        return z;
+    });
+    const A K = -m * z / (A(1) + m * ipow(w, Ls));
+    A pw = w;
+    col_pass<CB>(col, Ls, s0, ds, [&](A x) {
+        const A r = fmadd(K, pw, x);
+        pw *= w;
+        return r;
     });
 }
 
@@ -638,12 +665,30 @@ __device__ void column_phase(A* T, int tid, int sl, int s, int Ls, A (&v)[24], c
                              A scale, const Op5& op2, A mp, A mm) {
     put_row(T, tid, v);
     __syncthreads();
+    // the forms the solver uses take one or two passes per column: a
+    // bidiagonal op and an inverse in the same direction are fused, and the
+    // scale is folded into the coefficients (FP32 arithmetic only: in FP64
+    // the fused sweep costs the hop two more spilled registers, and measured
+    // slower)
+    const int k1 = std::is_same<A, double>::value ? -1 : op1.kind, k2 = op2.kind;
     for (int c = s; c < 24; c += Ls) {
         A* col = T + sl * Ls * STR + c;
         const bool upper = c < 12;
-        col_op<CB>(col, Ls, upper, op1, mp, mm);
-        if (scale != A(1)) col_pass<CB>(col, Ls, 0, 1, [&](A x) { return x * scale; });
-        col_op<CB>(col, Ls, upper, op2, mp, mm);
+        const A m = upper ? mp : mm;
+        const bool d1 = upper != (op1.tr != 0), d2 = upper != (op2.tr != 0);
+        if (k1 == 1 && k2 == 2 && d1 == d2) {
+            col_bidiag_inverse<CB>(col, Ls, d1, scale * (A)op1.a, scale * (A)op1.b, (A)op2.a, (A)op2.b, m);
+        } else if ((k1 == 1 && k2 == 0) || (k1 == 0 && k2 == 1)) {
+            const Op5& o = k1 ? op1 : op2;
+            col_bidiag<CB>(col, Ls, k1 ? d1 : d2, scale * (A)o.a, scale * (A)o.b, m);
+        } else if ((k1 == 2 && k2 == 0) || (k1 == 0 && k2 == 2)) {
+            const Op5& o = k1 ? op1 : op2;
+            col_inverse<CB>(col, Ls, k1 ? d1 : d2, (A)o.a, (A)o.b, m, scale);
+        } else {
+            col_op<CB>(col, Ls, upper, op1, mp, mm);
+            if (scale != A(1)) col_pass<CB>(col, Ls, 0, 1, [&](A x) { return x * scale; });
+            col_op<CB>(col, Ls, upper, op2, mp, mm);
+        }
     }
     __syncthreads();
     get_row(T, tid, v);
