@@ -162,6 +162,7 @@ struct eofa_ctx {
     int NS = 0, nblk_hop = 0, nblk_blas = 0;
     int* nbr = nullptr;
     int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
+    int blk[4] = {0, 0, 0, 0};   // the table lists whole 2x2x2x2 blocks (matrix-core paths)
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
     void* frag = nullptr;        // compact FP16 links for the matrix-core FP16 hop (4 | Ls)
@@ -319,7 +320,9 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.aux2_nrm = h.aux2 ? h.aux2->nrm : nullptr;
     a.nbr = c->nbr + (size_t)h.par * 8 * c->Vh;
     a.sites = c->sites[h.prec];
+    a.par = h.par;
     const bool mfma = (h.prec == P16 || h.prec == PB16) && c->Ls % 4 == 0 && c->use_mfma;
+    a.blk = mfma && h.hop && c->blk[h.prec];
     if (h.hop && !mfma) {   // the matrix-core paths read only their compact 16-bit links
         const int lp = link_prec(h.prec);
         a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
@@ -1572,61 +1575,89 @@ void free_ctx(eofa_ctx* c) {
 // Cache-blocked traversal of the hopping kernel.  XCD x (of 8) runs one
 // contiguous range of logical blocks (see xcd_block), so the site table is
 // laid out as 8 regions, one per XCD: the lattice is cut into parts[d]
-// pieces along y, z and t (their product is 8).  Inside a region the sites
-// are visited tile by tile; a tile spans the whole x extent and `ty`, `tz`,
-// `tt` along y, z, t (clamped to the region), except along `sweep`, which
-// the tile walks one slice at a time.  Every slice then needs the slices
-// before and after it along `sweep`, which are still in that XCD's L2, and
-// only the tile's faces across the other directions are read again by the
-// neighbouring tile.  Rows of x hold consecutive checkerboard indices, so
-// the table is the same for both parities.  The sweep may be cut into
+// pieces along x (in checkerboard positions), y, z and t (their product is
+// 8).  Inside a region the sites are visited tile by tile; a tile spans
+// `tx`, `ty`, `tz`, `tt` along x, y, z, t (clamped to the region; tx <= 0
+// means the region's whole x extent), except along `sweep`, which the tile
+// walks one slice at a time.  Every slice then needs the slices before and
+// after it along `sweep`, which are still in that XCD's L2, and only the
+// tile's faces across the other directions are read again by the
+// neighbouring tile.  A checkerboard index does not depend on the parity,
+// so the table is the same for both parities.  The sweep may be cut into
 // chunks of ext[sweep] slices.  Returns the natural order if the parts do
 // not divide the extents.
-struct Tiling { int parts[4], sweep, ext[3]; };   // dims 1 = y, 2 = z, 3 = t; parts[0] unused
+//
+// With `blocks` the same walk runs over the lattice of 2x2x2x2 blocks (parts
+// and tile extents count blocks), and every block contributes 8 consecutive
+// slots: its sites of either parity, slot j = b_y + 2 b_z + 4 b_t for
+// offsets b inside the block (a site's checkerboard index does not depend
+// on b_x).  Without a region split that divides the block lattice the blocks
+// are listed in natural order.
+struct Tiling { int parts[4], sweep, ext[3], tx; };   // dims 0 = x, 1 = y, 2 = z, 3 = t; ext: y, z, t
 
-std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
+std::vector<int> site_order(const eofa_ctx* c, const Tiling& T, bool blocks = false) {
     const int Vh = c->Vh, NS = c->NS, nslot = c->nblk_hop * NS;
     std::vector<int> ord;
     ord.reserve(nslot);
-    const int hx = c->L[0] / 2;   // checkerboard sites per x row
+    const int hx = c->L[0] / 2;   // checkerboard positions (or blocks) per x row
+    const int q = blocks ? 2 : 1;
+    const int E[4] = {hx, c->L[1] / q, c->L[2] / q, c->L[3] / q};   // extents in walk units
+    // x positions [x0, x1) of the walk row at (y, z, t) in walk units: sites, or blocks of 8 slots
+    auto emit = [&](int x0, int x1, int y, int z, int t) {
+        if (!blocks) {
+            const int cb0 = (c->L[0] * (y + c->L[1] * (z + c->L[2] * t))) / 2;
+            for (int i = x0; i < x1; ++i) ord.push_back(cb0 + i);
+            return;
+        }
+        for (int X = x0; X < x1; ++X)
+            for (int j = 0; j < 8; ++j) {
+                const int yy = 2 * y + (j & 1), zz = 2 * z + ((j >> 1) & 1), tt = 2 * t + (j >> 2);
+                ord.push_back(X + hx * (yy + c->L[1] * (zz + c->L[2] * tt)));
+            }
+    };
     bool ok = T.sweep >= 1 && T.sweep <= 3 && (c->L[0] % 2 == 0) &&
-              T.parts[1] * T.parts[2] * T.parts[3] == 8;
-    for (int d = 1; d < 4 && ok; ++d) ok = T.parts[d] >= 1 && c->L[d] % T.parts[d] == 0;
+              T.parts[0] * T.parts[1] * T.parts[2] * T.parts[3] == 8;
+    for (int d = 0; d < 4 && ok; ++d) ok = T.parts[d] >= 1 && E[d] % T.parts[d] == 0;
+    if (blocks && !ok) {
+        for (int t = 0; t < E[3]; ++t)
+            for (int z = 0; z < E[2]; ++z)
+                for (int y = 0; y < E[1]; ++y) emit(0, hx, y, z, t);
+    }
     if (ok) {
-        int lo[4] = {0, 0, 0, 0}, hi[4] = {c->L[0], c->L[1], c->L[2], c->L[3]};
-        int ext[4] = {c->L[0], T.ext[0], T.ext[1], T.ext[2]};
+        int lo[4] = {0, 0, 0, 0}, hi[4] = {E[0], E[1], E[2], E[3]};
+        int ext[4] = {T.tx, T.ext[0], T.ext[1], T.ext[2]};
         for (int d = 1; d < 4; ++d) if (ext[d] < 1) ext[d] = 1;
         int od[2], k = 0;   // the two non-sweep dims among y, z, t, slower one first
         for (int d = 3; d >= 1; --d) if (d != T.sweep) od[k++] = d;
         for (int X = 0; X < 8; ++X) {
             int r = X;
-            for (int d = 1; d < 4; ++d) {   // region of XCD X, y fastest
-                const int w = c->L[d] / T.parts[d], i = r % T.parts[d];
+            for (int d = 0; d < 4; ++d) {   // region of XCD X, x fastest
+                const int w = E[d] / T.parts[d], i = r % T.parts[d];
                 r /= T.parts[d];
                 lo[d] = i * w;
                 hi[d] = lo[d] + w;
             }
+            const int tx = ext[0] > 0 ? ext[0] : hi[0] - lo[0];
             // the sweep runs in chunks of ext[sweep] slices (all tiles of the
             // region visit one chunk before the next); <= 1 means one chunk
             const int cw = ext[T.sweep] > 1 ? ext[T.sweep] : hi[T.sweep] - lo[T.sweep];
             for (int c0 = lo[T.sweep]; c0 < hi[T.sweep]; c0 += cw)
             for (int a0 = lo[od[0]]; a0 < hi[od[0]]; a0 += ext[od[0]])
                 for (int a1 = lo[od[1]]; a1 < hi[od[1]]; a1 += ext[od[1]])
-                    for (int v = c0; v < std::min(c0 + cw, hi[T.sweep]); ++v) {
-                        int b[4], e[4];
-                        b[od[0]] = a0; e[od[0]] = std::min(a0 + ext[od[0]], hi[od[0]]);
-                        b[od[1]] = a1; e[od[1]] = std::min(a1 + ext[od[1]], hi[od[1]]);
-                        b[T.sweep] = v; e[T.sweep] = v + 1;
-                        for (int t = b[3]; t < e[3]; ++t)
-                            for (int z = b[2]; z < e[2]; ++z)
-                                for (int y = b[1]; y < e[1]; ++y) {
-                                    const int cb0 = (c->L[0] * (y + c->L[1] * (z + c->L[2] * t))) / 2;
-                                    for (int i = 0; i < hx; ++i) ord.push_back(cb0 + i);
-                                }
-                    }
+                    for (int x0 = lo[0]; x0 < hi[0]; x0 += tx)
+                        for (int v = c0; v < std::min(c0 + cw, hi[T.sweep]); ++v) {
+                            int b[4], e[4];
+                            b[od[0]] = a0; e[od[0]] = std::min(a0 + ext[od[0]], hi[od[0]]);
+                            b[od[1]] = a1; e[od[1]] = std::min(a1 + ext[od[1]], hi[od[1]]);
+                            b[T.sweep] = v; e[T.sweep] = v + 1;
+                            for (int t = b[3]; t < e[3]; ++t)
+                                for (int z = b[2]; z < e[2]; ++z)
+                                    for (int y = b[1]; y < e[1]; ++y) emit(x0, std::min(x0 + tx, hi[0]), y, z, t);
+                        }
         }
     }
     if ((int)ord.size() != Vh) {
+        if (blocks) fail(EOFA_EDEVICE, "internal: block traversal does not cover the lattice");
         ord.resize(Vh);
         for (int i = 0; i < Vh; ++i) ord[i] = i;
     }
@@ -1642,14 +1673,24 @@ std::vector<int> site_order(const eofa_ctx* c, const Tiling& T) {
 
 // Default tiling per precision (measured at 24^3x64, Ls = 24, and in a
 // model of the per-XCD L2): 8 slabs along z, tiles of 4 (FP16) or 8 (other
-// precisions) y rows by the slab's z planes, walked along t.  Tuning
-// overrides (dims given as y, z or t):
+// precisions) y rows by the slab's z planes, walked along t.  The block
+// traversal of the matrix-core paths (units of 2x2x2x2 blocks): 2 x 4
+// regions along y and z, each walked along t one block slice (the region's
+// whole x, y, z cross-section) at a time.  Tuning overrides (dims given as y, z or t; in blocks for
+// the block traversal):
 //   EOFA_TILE="split,ty,tz,tt,sweep"          8 slabs along `split` (e.g. "z,4,3,1,t")
 //   EOFA_TILE="p<py>,<pz>,<pt>,ty,tz,tt,sweep" py x pz x pt regions (e.g. "p1,2,4,6,12,1,t")
+//   EOFA_TILE="q<px>,<py>,<pz>,<pt>,tx,ty,tz,tt,sweep"  also split and tile x (tx <= 0: whole rows)
 //   EOFA_TILE="none"                          natural order
-Tiling default_tiling(const eofa_ctx* c, int prec) {
-    Tiling T{{1, 1, 1, 1}, 3, {prec == P16 ? 4 : 8, 1, 1}};
-    if (c->L[2] % 8 == 0) { T.parts[2] = 8; T.ext[1] = c->L[2] / 8; }
+Tiling default_tiling(const eofa_ctx* c, int prec, bool blocks) {
+    Tiling T{{1, 1, 1, 1}, 3, {prec == P16 ? 4 : 8, 1, 1}, 0};
+    if (blocks) {
+        const int by = c->L[1] / 2, bz = c->L[2] / 2, bt = c->L[3] / 2;
+        if (by % 2 == 0 && bz % 4 == 0) { T.parts[1] = 2; T.parts[2] = 4; T.ext[0] = by / 2; T.ext[1] = bz / 4; }
+        else if (bt % 8 == 0) { T.parts[3] = 8; T.ext[0] = 2; T.ext[1] = bz; }
+        else if (bz % 8 == 0) { T.parts[2] = 8; T.ext[0] = 2; T.ext[1] = bz / 8; }
+        else T.sweep = 0;   // natural order of the blocks
+    } else if (c->L[2] % 8 == 0) { T.parts[2] = 8; T.ext[1] = c->L[2] / 8; }
     else if (c->L[3] % 8 == 0) { T.parts[3] = 8; T.ext[0] = 6; T.ext[1] = 4; }
     else if (c->L[1] % 8 == 0) { T.parts[1] = 8; T.ext[0] = c->L[1] / 8; T.ext[1] = c->L[2]; }
     else T.sweep = 0;   // natural order
@@ -1657,10 +1698,13 @@ Tiling default_tiling(const eofa_ctx* c, int prec) {
         auto dim = [](char ch) { return ch == 'y' ? 1 : ch == 'z' ? 2 : ch == 't' ? 3 : 0; };
         char sp = 0, sw = 0;
         int py = 0, pz = 0, pt = 0, ty = 0, tz = 0, tt = 0;
-        if (sscanf(e, "p%d,%d,%d,%d,%d,%d,%c", &py, &pz, &pt, &ty, &tz, &tt, &sw) == 7) {
-            T = Tiling{{1, py, pz, pt}, dim(sw), {ty, tz, tt}};
+        int px = 0, tx = 0;
+        if (sscanf(e, "q%d,%d,%d,%d,%d,%d,%d,%d,%c", &px, &py, &pz, &pt, &tx, &ty, &tz, &tt, &sw) == 9) {
+            T = Tiling{{px, py, pz, pt}, dim(sw), {ty, tz, tt}, tx};
+        } else if (sscanf(e, "p%d,%d,%d,%d,%d,%d,%c", &py, &pz, &pt, &ty, &tz, &tt, &sw) == 7) {
+            T = Tiling{{1, py, pz, pt}, dim(sw), {ty, tz, tt}, 0};
         } else if (sscanf(e, "%c,%d,%d,%d,%c", &sp, &ty, &tz, &tt, &sw) == 5) {
-            T = Tiling{{1, 1, 1, 1}, dim(sw), {ty, tz, tt}};
+            T = Tiling{{1, 1, 1, 1}, dim(sw), {ty, tz, tt}, 0};
             if (dim(sp)) T.parts[dim(sp)] = 8;
         } else if (strcmp(e, "none") == 0) {
             T.sweep = 0;
@@ -1747,14 +1791,18 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             hipchk(hipMalloc((void**)&c->nbr, sizeof(int) * 2 * 8 * c->Vh), "hipMalloc(nbr)");
             hipchk(hipMalloc(&c->gauge[P64], (size_t)2 * 8 * 9 * c->Vh * 16), "hipMalloc(gauge)");
             hipchk(hipMalloc(&c->U_nat, (size_t)4 * c->V * 9 * 16), "hipMalloc(U)");
+            if (const char* e = getenv("EOFA_NO_MFMA")) c->use_mfma = atoi(e) == 0;
+            if (const char* e = getenv("EOFA_MFMA_DEPTH")) c->mfma_depth = atoi(e);
+            bool blocks_ok = c->use_mfma && c->Ls % 4 == 0 && c->NS % 8 == 0;
+            if (const char* e = getenv("EOFA_BLOCKS")) blocks_ok = blocks_ok && atoi(e) != 0;   // tuning
             for (int p = 0; p < 4; ++p) {
-                const std::vector<int> ord = site_order(c, default_tiling(c, p));
+                const bool blocks = blocks_ok && (p == P16 || p == PB16);
+                const std::vector<int> ord = site_order(c, default_tiling(c, p, blocks), blocks);
+                c->blk[p] = blocks;
                 hipchk(hipMalloc((void**)&c->sites[p], sizeof(int) * ord.size()), "hipMalloc(site table)");
                 hipchk(hipMemcpy(c->sites[p], ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice),
                        "copy site table");
             }
-            if (const char* e = getenv("EOFA_NO_MFMA")) c->use_mfma = atoi(e) == 0;
-            if (const char* e = getenv("EOFA_MFMA_DEPTH")) c->mfma_depth = atoi(e);
             c->om_h.resize(c->Ls);
             for (int s = 0; s < c->Ls; ++s) c->om_h[s] = std::pow(-c->c5 / c->b5, s);
             hipchk(hipMalloc((void**)&c->om, sizeof(double) * c->Ls), "hipMalloc(omega)");

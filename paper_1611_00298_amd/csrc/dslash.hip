@@ -294,10 +294,10 @@ __device__ __forceinline__ h2v mul_i(h2v y) {   // i y
 __device__ __forceinline__ h4v cat(h2v a, h2v b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3); }
 __device__ __forceinline__ h4v h4_of(uint32_t a, uint32_t b) { return cat(as_h2(a), as_h2(b)); }
 
-// h_j (j = 0, 1) for colours c = 0..2 from the raw words w[3k + c]
-template <int MU, int SG>
-__device__ __forceinline__ void project_h2(const uint32_t (&w)[12], h2v (&h)[6]) {
-    const _Float16 sg = (_Float16)SG;
+// h_j (j = 0, 1) for colours c = 0..2 from the raw words w[3k + c]; sg = +-1
+// (a constant on the fixed-direction paths, per lane on the block path)
+template <int MU>
+__device__ __forceinline__ void project_h2(const uint32_t (&w)[12], _Float16 sg, h2v (&h)[6]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const h2v p0 = as_h2(w[c]), p1 = as_h2(w[3 + c]), p2 = as_h2(w[6 + c]), p3 = as_h2(w[9 + c]);
@@ -313,10 +313,9 @@ __device__ __forceinline__ void project_h2(const uint32_t (&w)[12], h2v (&h)[6])
     }
 }
 
-// acc_up += f u ; acc_lo += f sg A^dag u  (FMAs)
-template <int MU, int SG>
-__device__ __forceinline__ void reconstruct_f(const float (&u)[12], float f, float (&acc)[24]) {
-    const float g = SG * f;
+// acc_up += f u ; acc_lo += g A^dag u with g = sg f  (FMAs)
+template <int MU>
+__device__ __forceinline__ void reconstruct_f(const float (&u)[12], float f, float g, float (&acc)[24]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const float r0 = u[2 * c], i0 = u[2 * c + 1];
@@ -361,14 +360,13 @@ __device__ __forceinline__ void load_mstage(const HopArgs& a, int s, int nb, MSt
     else st.nrm = 1.0f;
 }
 
-// lrec: the staged link record of this direction (8 rows of 16 bytes)
-template <bool DAG, int D>
-__device__ __forceinline__ void compute_mstage(const MStage& st, const unsigned char* lrec, int lane4,
+// Direction mu, sign sg = +-1 of the projector (1 + sg gamma_mu); lrec: the
+// staged link record of this direction (8 rows of 16 bytes)
+template <int MU>
+__device__ __forceinline__ void compute_mstage(const MStage& st, const unsigned char* lrec, int lane4, float sg,
                                                float (&acc)[24]) {
-    constexpr int MU = D & 3;
-    constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
     h2v h[6];
-    project_h2<MU, SG>(st.w, h);
+    project_h2<MU>(st.w, (_Float16)sg, h);
     const uint4 r0 = *reinterpret_cast<const uint4*>(lrec + 16 * lane4);
     const uint4 r1 = *reinterpret_cast<const uint4*>(lrec + 64 + 16 * lane4);
     const h4v A00 = h4_of(r0.x, r0.y), A01 = h4_of(r0.z, r0.w);
@@ -387,7 +385,7 @@ __device__ __forceinline__ void compute_mstage(const MStage& st, const unsigned 
         u[6 * j + 0] = c0[0]; u[6 * j + 1] = c0[1]; u[6 * j + 2] = c0[2]; u[6 * j + 3] = c0[3];
         u[6 * j + 4] = c1[0]; u[6 * j + 5] = c1[1];
     }
-    reconstruct_f<MU, SG>(u, st.nrm, acc);
+    reconstruct_f<MU>(u, st.nrm, sg * st.nrm, acc);
 }
 
 // BF16 on the matrix cores: the spin projection runs in FP32 on the
@@ -407,31 +405,29 @@ __device__ __forceinline__ uint32_t pack_b16(float re, float im) {
 
 // h_j (j = 0, 1) for colours c = 0..2 as packed (re, im) BF16 words, the
 // same projection as project() on the stored words
-template <int MU, int SG>
-__device__ __forceinline__ void project_b16(const uint32_t (&w)[12], uint32_t (&h)[6]) {
+template <int MU>
+__device__ __forceinline__ void project_b16(const uint32_t (&w)[12], float sg, uint32_t (&h)[6]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const float r0 = b16lo(w[c]), i0 = b16hi(w[c]), r1 = b16lo(w[3 + c]), i1 = b16hi(w[3 + c]);
         const float r2 = b16lo(w[6 + c]), i2 = b16hi(w[6 + c]), r3 = b16lo(w[9 + c]), i3 = b16hi(w[9 + c]);
         if constexpr (MU == 0) {
-            h[c] = pack_b16(r0 + SG * i3, i0 - SG * r3);  h[3 + c] = pack_b16(r1 + SG * i2, i1 - SG * r2);
+            h[c] = pack_b16(r0 + sg * i3, i0 - sg * r3);  h[3 + c] = pack_b16(r1 + sg * i2, i1 - sg * r2);
         } else if constexpr (MU == 1) {
-            h[c] = pack_b16(r0 - SG * r3, i0 - SG * i3);  h[3 + c] = pack_b16(r1 + SG * r2, i1 + SG * i2);
+            h[c] = pack_b16(r0 - sg * r3, i0 - sg * i3);  h[3 + c] = pack_b16(r1 + sg * r2, i1 + sg * i2);
         } else if constexpr (MU == 2) {
-            h[c] = pack_b16(r0 + SG * i2, i0 - SG * r2);  h[3 + c] = pack_b16(r1 - SG * i3, i1 + SG * r3);
+            h[c] = pack_b16(r0 + sg * i2, i0 - sg * r2);  h[3 + c] = pack_b16(r1 - sg * i3, i1 + sg * r3);
         } else {
-            h[c] = pack_b16(r0 + SG * r2, i0 + SG * i2);  h[3 + c] = pack_b16(r1 + SG * r3, i1 + SG * i3);
+            h[c] = pack_b16(r0 + sg * r2, i0 + sg * i2);  h[3 + c] = pack_b16(r1 + sg * r3, i1 + sg * i3);
         }
     }
 }
 
-template <bool DAG, int D>
-__device__ __forceinline__ void compute_mstage_b16(const MStage& st, const unsigned char* lrec, int lane4,
+template <int MU>
+__device__ __forceinline__ void compute_mstage_b16(const MStage& st, const unsigned char* lrec, int lane4, float sg,
                                                    float (&acc)[24]) {
-    constexpr int MU = D & 3;
-    constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
     uint32_t h[6];
-    project_b16<MU, SG>(st.w, h);
+    project_b16<MU>(st.w, sg, h);
     const uint4 r0 = *reinterpret_cast<const uint4*>(lrec + 16 * lane4);
     const uint4 r1 = *reinterpret_cast<const uint4*>(lrec + 64 + 16 * lane4);
     const s4v A00 = s4_of(r0.x, r0.y), A01 = s4_of(r0.z, r0.w);
@@ -449,15 +445,22 @@ __device__ __forceinline__ void compute_mstage_b16(const MStage& st, const unsig
         u[6 * j + 0] = c0[0]; u[6 * j + 1] = c0[1]; u[6 * j + 2] = c0[2]; u[6 * j + 3] = c0[3];
         u[6 * j + 4] = c1[0]; u[6 * j + 5] = c1[1];
     }
-    reconstruct_f<MU, SG>(u, 1.0f, acc);
+    reconstruct_f<MU>(u, 1.0f, sg, acc);
+}
+
+// direction mu with a per-lane projector sign
+template <int P, int MU>
+__device__ __forceinline__ void compute_mstage_sg(const MStage& st, const unsigned char* lrec, int lane4, float sg,
+                                                  float (&acc)[24]) {
+    if constexpr (P == P16) compute_mstage<MU>(st, lrec, lane4, sg, acc);
+    else compute_mstage_b16<MU>(st, lrec, lane4, sg, acc);
 }
 
 template <int P, bool DAG>
 __device__ __forceinline__ void compute_mstage_rt(const MStage& st, int d, const unsigned char* lrec, int lane4,
                                                   float (&acc)[24]) {
-#define EOFA_MSTAGE(DD)                                                   \
-    if constexpr (P == P16) compute_mstage<DAG, DD>(st, lrec, lane4, acc); \
-    else compute_mstage_b16<DAG, DD>(st, lrec, lane4, acc);
+#define EOFA_MSTAGE(DD) \
+    compute_mstage_sg<P, (DD) & 3>(st, lrec, lane4, (float)(((DD) < 4 ? -1 : 1) * (DAG ? -1 : 1)), acc);
     switch (d) {   // d is a compile-time constant after unrolling
     case 0: EOFA_MSTAGE(0) break;
     case 1: EOFA_MSTAGE(1) break;
@@ -491,6 +494,98 @@ __device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int lb, unsigned 
         compute_mstage_rt<P, DAG>(st[d % DEPTH], d, lr + d * LB, lane4, acc);
         if (d + DEPTH < 8) load_mstage<P>(a, s, nb[d + DEPTH], st[d % DEPTH]);
     }
+}
+
+// LDS bytes of the block path's shared neighbour spinors, after the links:
+// [3][NT] words of 16 bytes, then [NT] FP16 site norms
+__host__ __device__ constexpr size_t share_bytes(int NT) { return (size_t)NT * 52; }
+
+// The same eight directions when the workgroup holds whole 2x2x2x2 blocks of
+// the lattice (blocks at even coordinates; the site table lists the 8 sites
+// of the output parity of each block, slot j = b_y + 2 b_z + 4 b_t with b the
+// site's offsets in its block, and b_x = (b_y + b_z + b_t + parity) mod 2).
+// Along every direction mu one neighbour of a site lies inside its block
+// (+mu if b_mu = 0, -mu if b_mu = 1) and the other outside.  The inside
+// neighbour along x is the block's opposite-parity site with the same slot
+// j; each work-item loads that one (its slice s) and shares it through LDS,
+// where the inside neighbours along y, z and t are those of slots j^1, j^2
+// and j^4.  A work-item so gathers 5 neighbour spinors from memory instead
+// of 8; the four outside ones keep DEPTH in flight.  The projector signs
+// depend on the site's offsets and are applied per lane.
+// The same eight directions when the workgroup holds whole 2x2x2x2 blocks of
+// the lattice (blocks at even coordinates; the site table lists the 8 sites
+// of the output parity of each block, slot j = b_y + 2 b_z + 4 b_t with b the
+// site's offsets in its block, and b_x = (b_y + b_z + b_t + parity) mod 2).
+// Along every direction mu one neighbour of a site lies inside its block
+// (+mu if b_mu = 0, -mu if b_mu = 1) and the other outside.  The inside
+// neighbour along x is the block's opposite-parity site with the same slot
+// j; each work-item loads that one (its slice s) and shares it through LDS,
+// where the inside neighbours along y, z and t are those of slots j^1, j^2
+// and j^4.  A work-item so gathers 5 neighbour spinors from memory instead
+// of 8.  The projector signs depend on the site's offsets and are applied
+// per lane.  Order: inside x, then outside and inside directions
+// alternating, with two outside spinors in flight besides the one read from
+// LDS (the register budget of the 5-wave FP16 kernel).
+template <int P, bool DAG>
+__device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned char* lds, int site, int sl, int s,
+                                             int lane4, float (&acc)[24]) {
+    constexpr int LB = LinkLds<P, 1>::LB;
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int j = sl & 7;
+    const int off = (j << 1) | ((__popc(j) + a.par) & 1);   // b_x + 2 b_y + 4 b_z + 8 b_t
+    // inside direction of mu: mu (forward, projector sign -1) if b_mu = 0,
+    // mu + 4 (backward, +1) if b_mu = 1; the outside direction is the other
+    auto din = [&](int mu) { return mu + 4 * ((off >> mu) & 1); };
+    auto sgn = [&](int d) { return (d < 4 ? -1.f : 1.f) * (DAG ? -1.f : 1.f); };
+    auto nbr_of = [&](int d) { return a.nbr[(size_t)d * a.Vh + site]; };
+    const int nbx = nbr_of(din(0));
+    int nbo[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) nbo[mu] = nbr_of(din(mu) ^ 4);
+    MStage sx, o[2];
+    load_mstage<P>(a, s, nbx, sx);
+    load_mstage<P>(a, s, nbo[0], o[0]);
+    load_mstage<P>(a, s, nbo[1], o[1]);
+    stage_links<P, 1>(a, lb, lds);
+    uint4* sh = reinterpret_cast<uint4*>(lds + stage_bytes(LB, a.NS));
+    float* shn = reinterpret_cast<float*>(sh + 3 * NT);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) sh[b * NT + tid] = make_uint4(sx.w[4 * b], sx.w[4 * b + 1], sx.w[4 * b + 2], sx.w[4 * b + 3]);
+    if constexpr (P == P16) shn[tid] = sx.nrm;
+    __syncthreads();
+    const unsigned char* lr = lds + sl * 8 * LB;
+    auto inside = [&](auto mu_c) {   // inside neighbour along y, z or t, from LDS
+        constexpr int MU = decltype(mu_c)::value;
+        const int src = (sl ^ (1 << (MU - 1))) * a.Ls + s;
+        MStage t;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const uint4 q = sh[b * NT + src];
+            t.w[4 * b] = q.x; t.w[4 * b + 1] = q.y; t.w[4 * b + 2] = q.z; t.w[4 * b + 3] = q.w;
+        }
+        t.nrm = P == P16 ? shn[src] : 1.0f;
+        const int d = din(MU);
+        compute_mstage_sg<P, MU>(t, lr + d * LB, lane4, sgn(d), acc);
+    };
+    auto outside = [&](auto mu_c, const MStage& st) {
+        constexpr int MU = decltype(mu_c)::value;
+        const int d = din(MU) ^ 4;
+        compute_mstage_sg<P, MU>(st, lr + d * LB, lane4, sgn(d), acc);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    compute_mstage_sg<P, 0>(sx, lr + din(0) * LB, lane4, sgn(din(0)), acc);
+    outside(I0{}, o[0]);
+    load_mstage<P>(a, s, nbo[2], o[0]);
+    inside(I1{});
+    outside(I1{}, o[1]);
+    load_mstage<P>(a, s, nbo[3], o[1]);
+    inside(I2{});
+    outside(I2{}, o[0]);
+    inside(I3{});
+    outside(I3{}, o[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -710,7 +805,7 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
     return t;
 }
 
-template <int P, bool DAG, bool HOP, int MF, bool DENSE = false>
+template <int P, bool DAG, bool HOP, int MF, bool DENSE = false, bool BLK = false>
 __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) k_hop(const HopArgs a) {
     using A = typename PT<P>::A;
     // column-sweep load batch: what each variant's register budget allows
@@ -739,7 +834,8 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) 
             stage_links<P, 0>(a, lb, smem_raw);
             __syncthreads();
         }
-        if constexpr (MF) hop_all_mfma<P, DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
+        if constexpr (MF && BLK) hop_blk_mfma<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
+        else if constexpr (MF) hop_all_mfma<P, DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
         else if constexpr (P == P64) { if (active) hop_all<P, DAG>(a, lb, smem_raw, site, sl, s, v); }
         else hop_all<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
         if (!active) {
@@ -947,7 +1043,11 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     const size_t tile = need_lds ? (size_t)STR * NT * sizeof(A) : 0;
     if constexpr ((P == P16 || P == PB16) && HOP) {
         if (a.frag) {
-            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 1>::LB, a.NS));
+            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 1>::LB, a.NS) + (a.blk ? share_bytes(NT) : 0));
+            if (a.blk) {   // the block path keeps its own loads in flight
+                hipLaunchKernelGGL((k_hop<P, DAG, HOP, 3, false, true>), dim3(nblk), dim3(NT), shm, st, a);
+                return hipGetLastError();
+            }
             if (a.depth >= 4) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 4>), dim3(nblk), dim3(NT), shm, st, a);
             else if (a.depth == 3) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 3>), dim3(nblk), dim3(NT), shm, st, a);
             else hipLaunchKernelGGL((k_hop<P, DAG, HOP, 2>), dim3(nblk), dim3(NT), shm, st, a);

@@ -268,6 +268,8 @@ struct HopArgs {
     const int* sites;    // traversal: slot lb*NS + sl -> output site, >= Vh for padding (nullable)
     const void* frag;    // compact FP16 links for the matrix-core path, [8][Vh][9] (re, im) halves (nullable)
     int depth;           // directions of operands kept in flight (matrix-core path)
+    int par;             // parity of the output sites
+    int blk;             // matrix-core path: the site table lists whole 2x2x2x2 blocks, 8 slots each
     int Vh, Ls, NS;
     size_t N;
     double mp, mm;
