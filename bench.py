@@ -89,8 +89,10 @@ def measured_traffic(inner, workload):
         return None
 
 
-HOP_TEMPLATE = {"fp64": "k_hop<0, {}, true, 0, false>", "fp32": "k_hop<1, {}, true, 0, false>",
-                "fp16": "k_hop<2, {}, true, 3, false>", "bf16": "k_hop<3, {}, true, 3, false>"}
+# kernel-name prefixes of the hopping kernel per inner precision (the last
+# template argument, the block-sharing variant, is left open)
+HOP_TEMPLATE = {"fp64": "k_hop<0, {}, true, 0, false,", "fp32": "k_hop<1, {}, true, 0, false,",
+                "fp16": "k_hop<2, {}, true, 3, false,", "bf16": "k_hop<3, {}, true, 3, false,"}
 
 
 def profile_summary(args):
@@ -162,7 +164,7 @@ def profile_summary(args):
         return 64 * c.get("TCC_EA0_WRREQ_64B_sum", 0) + 32 * (c.get("TCC_EA0_WRREQ_sum", 0) -
                                                               c.get("TCC_EA0_WRREQ_64B_sum", 0))
     avg = lambda xs: sum(xs) / len(xs) if xs else float("nan")
-    lines = [f"# {HOP_TEMPLATE[args.inner].format('*')} (the {args.inner} hopping kernel), bench.py, "
+    lines = [f"# {HOP_TEMPLATE[args.inner].format('*')} *> (the {args.inner} hopping kernel), bench.py, "
              f"{Lx}x{Ly}x{Lz}x{Lt}, Ls={pre['Ls']}, per launch",
              "# read bytes = 128 TCC_EA0_RDREQ_128B + 64 TCC_EA0_RDREQ_64B + 32 TCC_EA0_RDREQ_32B;",
              "# write bytes = 64 TCC_EA0_WRREQ_64B + 32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B)  (no calibration factor)"]
