@@ -162,7 +162,7 @@ struct eofa_ctx {
     int NS = 0, nblk_hop = 0, nblk_blas = 0;
     int* nbr = nullptr;
     int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
-    int blk[4] = {0, 0, 0, 0};   // the table lists whole 2x2x2x2 blocks (matrix-core paths)
+    int blk[4] = {0, 0, 0, 0};   // the table lists whole 2x2x2x2 blocks (FP32 and matrix-core paths)
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
     void* frag = nullptr;        // compact FP16 links for the matrix-core FP16 hop (4 | Ls)
@@ -322,7 +322,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.sites = c->sites[h.prec];
     a.par = h.par;
     const bool mfma = (h.prec == P16 || h.prec == PB16) && c->Ls % 4 == 0 && c->use_mfma;
-    a.blk = mfma && h.hop && c->blk[h.prec];
+    a.blk = (mfma || h.prec == P32) && h.hop && c->blk[h.prec];
     if (h.hop && !mfma) {   // the matrix-core paths read only their compact 16-bit links
         const int lp = link_prec(h.prec);
         a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
@@ -1793,10 +1793,13 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             hipchk(hipMalloc(&c->U_nat, (size_t)4 * c->V * 9 * 16), "hipMalloc(U)");
             if (const char* e = getenv("EOFA_NO_MFMA")) c->use_mfma = atoi(e) == 0;
             if (const char* e = getenv("EOFA_MFMA_DEPTH")) c->mfma_depth = atoi(e);
-            bool blocks_ok = c->use_mfma && c->Ls % 4 == 0 && c->NS % 8 == 0;
+            // block traversal (and block-sharing hops): the FP32 path and the
+            // matrix-core paths, whenever a workgroup holds whole 2x2x2x2 blocks
+            bool blocks_ok = c->NS % 8 == 0;
             if (const char* e = getenv("EOFA_BLOCKS")) blocks_ok = blocks_ok && atoi(e) != 0;   // tuning
+            const bool mf_ok = c->use_mfma && c->Ls % 4 == 0;
             for (int p = 0; p < 4; ++p) {
-                const bool blocks = blocks_ok && (p == P16 || p == PB16);
+                const bool blocks = blocks_ok && (p == P32 || (mf_ok && (p == P16 || p == PB16)));
                 const std::vector<int> ord = site_order(c, default_tiling(c, p, blocks), blocks);
                 c->blk[p] = blocks;
                 hipchk(hipMalloc((void**)&c->sites[p], sizeof(int) * ord.size()), "hipMalloc(site table)");

@@ -27,8 +27,8 @@ namespace eofa {
 // A_x = -i sigma_x, A_y = -i sigma_y, A_z = -i sigma_z, A_t = 1.
 // (1 + sg gamma_mu) psi = (h ; sg A^dag h),  h = psi_up + sg A psi_lo.
 // ---------------------------------------------------------------------------
-template <int MU, int SG, typename A>
-__device__ __forceinline__ void project(const A (&p)[24], A (&h)[12]) {
+template <int MU, typename A>
+__device__ __forceinline__ void project(const A (&p)[24], A SG, A (&h)[12]) {
     // complex (spin k, colour c): re = p[2*(3k+c)], im = +1
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -52,9 +52,10 @@ __device__ __forceinline__ void project(const A (&p)[24], A (&h)[12]) {
     }
 }
 
-// acc_up += u ; acc_lo += sg A^dag u
-template <int MU, int SG, typename A>
-__device__ __forceinline__ void reconstruct(const A (&u)[12], A (&acc)[24]) {
+// acc_up += u ; acc_lo += sg A^dag u  (sg = +-1: a constant on the
+// fixed-direction paths, per lane on the block paths)
+template <int MU, typename A>
+__device__ __forceinline__ void reconstruct(const A (&u)[12], A SG, A (&acc)[24]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const A r0 = u[2 * c], i0 = u[2 * c + 1];
@@ -195,26 +196,32 @@ __device__ __forceinline__ void load_stage(const HopArgs& a, int s, int nb, Stag
     else ld_spinor<P>(a.in, a.in_nrm, a.N, n, st.psi);
 }
 
-template <int P, bool DAG, int D>
-__device__ __forceinline__ void compute_stage(const Stage<P>& st, const unsigned char* lrec,
-                                              typename PT<P>::A (&acc)[24]) {
+// direction mu, projector sign sg = +-1 (per lane on the block paths)
+template <int P, int MU>
+__device__ __forceinline__ void compute_stage_sg(const Stage<P>& st, const unsigned char* lrec,
+                                                 typename PT<P>::A sg, typename PT<P>::A (&acc)[24]) {
     using A = typename PT<P>::A;
-    constexpr int MU = D & 3;
-    constexpr int SG = (D < 4 ? -1 : 1) * (DAG ? -1 : 1);
     using L = typename PT<link_prec(P)>::A;
     const L* ul = reinterpret_cast<const L*>(lrec);
     A U[18];
 #pragma unroll
     for (int k = 0; k < 18; ++k) U[k] = (A)ul[k];
     A h[12];
-    project<MU, SG>(st.psi, h);
+    project<MU>(st.psi, sg, h);
     if constexpr (P == P16) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) h[k] *= st.nrm;
     }
     A u[12];
     su3_mul(U, h, u);
-    reconstruct<MU, SG>(u, acc);
+    reconstruct<MU>(u, sg, acc);
+}
+
+template <int P, bool DAG, int D>
+__device__ __forceinline__ void compute_stage(const Stage<P>& st, const unsigned char* lrec,
+                                              typename PT<P>::A (&acc)[24]) {
+    using A = typename PT<P>::A;
+    compute_stage_sg<P, D & 3>(st, lrec, (A)((D < 4 ? -1 : 1) * (DAG ? -1 : 1)), acc);
 }
 
 template <int P, bool DAG>
@@ -266,6 +273,95 @@ __device__ __forceinline__ void hop_all(const HopArgs& a, int lb, unsigned char*
         compute_stage_rt<P, DAG>(st[d % DEPTH], d, lr + d * LB, acc);
         if (d + DEPTH < 8) load_stage<P>(a, s, nb[d + DEPTH], st[d % DEPTH]);
     }
+}
+
+// LDS bytes of the block paths' shared neighbour spinors, after the links:
+// the matrix-core paths keep the raw 16-bit words ([3][NT] words of 16
+// bytes, then [NT] FP16 site norms), the vector paths the spinor at the
+// arithmetic precision ([24 sizeof(A) / 16][NT] words of 16 bytes)
+__host__ __device__ constexpr size_t share_bytes(int P, bool mf, int NT) {
+    return (size_t)NT * (mf ? 52 : (P == P64 ? 192 : 96));
+}
+
+// The block form of the vector paths: the workgroup holds whole
+// 2x2x2x2 blocks, listed by the site table as for the matrix-core block path
+// below (slot j = b_y + 2 b_z + 4 b_t, b_x = (b_y + b_z + b_t + parity) mod
+// 2).  Along every direction mu one neighbour lies inside the block (+mu if
+// b_mu = 0, -mu if b_mu = 1).  Each work-item loads its inside neighbour
+// along x (the block's opposite-parity site in the same slot) and shares it
+// through LDS, where the inside neighbours along y, z and t are those of
+// slots j^1, j^2 and j^4; the four outside neighbours come from memory, two
+// in flight.  5 gathers per work-item instead of 8.  Used for FP32: in FP64
+// the shared spinors (192 B per work-item) and the FP64 links need 46 KB of
+// LDS per workgroup, one workgroup per CU fewer than the per-site form, which
+// cancels the gain (measured 1.76-1.77 against 1.75 ms at 24^3x64, Ls = 24).
+template <int P, bool DAG>
+__device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned char* lds, int site, int sl, int s,
+                                            typename PT<P>::A (&acc)[24]) {
+    using A = typename PT<P>::A;
+    constexpr int LB = LinkLds<P, 0>::LB;
+    constexpr int CH = 24 * (int)sizeof(A) / 16;   // 16-byte words per spinor
+    constexpr int K = 16 / (int)sizeof(A);          // reals per word
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int j = sl & 7;
+    const int off = (j << 1) | ((__popc(j) + a.par) & 1);   // b_x + 2 b_y + 4 b_z + 8 b_t
+    auto din = [&](int mu) { return mu + 4 * ((off >> mu) & 1); };
+    auto sgn = [&](int d) { return (A)((d < 4 ? -1 : 1) * (DAG ? -1 : 1)); };
+    auto nbr_of = [&](int d) { return a.nbr[(size_t)d * a.Vh + site]; };
+    uint4* sh = reinterpret_cast<uint4*>(lds + stage_bytes(LB, a.NS));
+    auto put = [&](const Stage<P>& st) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            A w[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) w[k] = st.psi[K * c + k];
+            sh[c * NT + tid] = __builtin_bit_cast(uint4, w);
+        }
+    };
+    auto get = [&](int src, Stage<P>& st) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            struct W { A v[K]; };
+            const W w = __builtin_bit_cast(W, sh[c * NT + src]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) st.psi[K * c + k] = w.v[k];
+        }
+    };
+    const unsigned char* lr = lds + sl * 8 * LB;
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    auto inside = [&](auto mu_c, Stage<P>& t) {   // inside neighbour along y, z or t, from LDS
+        constexpr int MU = decltype(mu_c)::value;
+        get((sl ^ (1 << (MU - 1))) * a.Ls + s, t);
+        compute_stage_sg<P, MU>(t, lr + din(MU) * LB, sgn(din(MU)), acc);
+    };
+    auto outside = [&](auto mu_c, const Stage<P>& t) {
+        constexpr int MU = decltype(mu_c)::value;
+        const int d = din(MU) ^ 4;
+        compute_stage_sg<P, MU>(t, lr + d * LB, sgn(d), acc);
+    };
+    int nbo[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) nbo[mu] = nbr_of(din(mu) ^ 4);
+    Stage<P> sx, o[2];
+    load_stage<P>(a, s, nbr_of(din(0)), sx);
+    load_stage<P>(a, s, nbo[0], o[0]);
+    load_stage<P>(a, s, nbo[1], o[1]);
+    stage_links<P, 0>(a, lb, lds);
+    put(sx);
+    __syncthreads();
+    compute_stage_sg<P, 0>(sx, lr + din(0) * LB, sgn(din(0)), acc);
+    outside(I0{}, o[0]);
+    load_stage<P>(a, s, nbo[2], o[0]);
+    inside(I1{}, sx);
+    outside(I1{}, o[1]);
+    load_stage<P>(a, s, nbo[3], o[1]);
+    inside(I2{}, sx);
+    outside(I2{}, o[0]);
+    inside(I3{}, sx);
+    outside(I3{}, o[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,10 +591,6 @@ __device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int lb, unsigned 
         if (d + DEPTH < 8) load_mstage<P>(a, s, nb[d + DEPTH], st[d % DEPTH]);
     }
 }
-
-// LDS bytes of the block path's shared neighbour spinors, after the links:
-// [3][NT] words of 16 bytes, then [NT] FP16 site norms
-__host__ __device__ constexpr size_t share_bytes(int NT) { return (size_t)NT * 52; }
 
 // The same eight directions when the workgroup holds whole 2x2x2x2 blocks of
 // the lattice (blocks at even coordinates; the site table lists the 8 sites
@@ -836,6 +928,7 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) 
         }
         if constexpr (MF && BLK) hop_blk_mfma<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
         else if constexpr (MF) hop_all_mfma<P, DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
+        else if constexpr (BLK) hop_blk_vec<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
         else if constexpr (P == P64) { if (active) hop_all<P, DAG>(a, lb, smem_raw, site, sl, s, v); }
         else hop_all<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
         if (!active) {
@@ -1043,7 +1136,7 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
     const size_t tile = need_lds ? (size_t)STR * NT * sizeof(A) : 0;
     if constexpr ((P == P16 || P == PB16) && HOP) {
         if (a.frag) {
-            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 1>::LB, a.NS) + (a.blk ? share_bytes(NT) : 0));
+            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 1>::LB, a.NS) + (a.blk ? share_bytes(P, true, NT) : 0));
             if (a.blk) {   // the block path keeps its own loads in flight
                 hipLaunchKernelGGL((k_hop<P, DAG, HOP, 3, false, true>), dim3(nblk), dim3(NT), shm, st, a);
                 return hipGetLastError();
@@ -1051,6 +1144,13 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
             if (a.depth >= 4) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 4>), dim3(nblk), dim3(NT), shm, st, a);
             else if (a.depth == 3) hipLaunchKernelGGL((k_hop<P, DAG, HOP, 3>), dim3(nblk), dim3(NT), shm, st, a);
             else hipLaunchKernelGGL((k_hop<P, DAG, HOP, 2>), dim3(nblk), dim3(NT), shm, st, a);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (P == P32 && HOP) {
+        if (a.blk) {
+            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 0>::LB, a.NS) + share_bytes(P, false, NT));
+            hipLaunchKernelGGL((k_hop<P, DAG, HOP, 0, false, true>), dim3(nblk), dim3(NT), shm, st, a);
             return hipGetLastError();
         }
     }
