@@ -66,7 +66,7 @@ __device__ __forceinline__ void force_from_B(const cplx (&B)[9], const double2* 
     }
 }
 
-// Work-item (site, s) of parity p = blockIdx.y, workgroups of NS whole sites
+// Work-item (site, s) of parity p, workgroups of NS whole sites
 // x Ls slices in the traversal of the FP64 hop (site table, XCD ranges).
 // chi_L, chi_R in the FP64 device layout (block c of 5D site n at
 // base[c N + n], n = cb Ls + s).  For each system and direction mu every
@@ -84,9 +84,12 @@ __global__ void __launch_bounds__(256, 3) k_force_dev(const double2* __restrict_
                                                    int NS, size_t N) {
     extern __shared__ double red[];   // [NT][19] slice terms, then [4][NS][18] sums
     const int NT = blockDim.x, tid = threadIdx.x, Ls = g.Ls;
-    const int p = blockIdx.y;
     const int sl = tid / Ls, s = tid - sl * Ls;
-    const int lb = xcd_block(gridDim.x);
+    // the two parities of a slot range run back to back on one XCD, so the
+    // spinors one reads as neighbours are still in L2 when the other reads
+    // them as its own sites
+    const int lbp = xcd_block(gridDim.x);
+    const int p = lbp & 1, lb = lbp >> 1;
     const int slot = lb * NS + sl;
     const int cb = sites ? sites[slot] : slot;
     const bool active = cb < g.Vh;
@@ -250,7 +253,7 @@ hipError_t launch_force(const void* U, const void* chiLe, const void* chiLo, con
     g.aperiodic = aperiodic;
     const int NT = NS * Ls;
     const size_t shm = sizeof(double) * ((size_t)NT * 19 + (size_t)4 * NS * 18);
-    hipLaunchKernelGGL(k_force_dev, dim3(nblk, 2), dim3(NT), shm, st, (const double2*)chiLe,
+    hipLaunchKernelGGL(k_force_dev, dim3(2 * nblk), dim3(NT), shm, st, (const double2*)chiLe,
                        (const double2*)chiLo, (const double2*)chiRe, (const double2*)chiRo, (const double2*)U,
                        nbr, sites, k, (double2*)F, (double2*)G, g, NS, N);
     return hipGetLastError();
