@@ -602,18 +602,6 @@ __device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int lb, unsigned 
 // j; each work-item loads that one (its slice s) and shares it through LDS,
 // where the inside neighbours along y, z and t are those of slots j^1, j^2
 // and j^4.  A work-item so gathers 5 neighbour spinors from memory instead
-// of 8; the four outside ones keep DEPTH in flight.  The projector signs
-// depend on the site's offsets and are applied per lane.
-// The same eight directions when the workgroup holds whole 2x2x2x2 blocks of
-// the lattice (blocks at even coordinates; the site table lists the 8 sites
-// of the output parity of each block, slot j = b_y + 2 b_z + 4 b_t with b the
-// site's offsets in its block, and b_x = (b_y + b_z + b_t + parity) mod 2).
-// Along every direction mu one neighbour of a site lies inside its block
-// (+mu if b_mu = 0, -mu if b_mu = 1) and the other outside.  The inside
-// neighbour along x is the block's opposite-parity site with the same slot
-// j; each work-item loads that one (its slice s) and shares it through LDS,
-// where the inside neighbours along y, z and t are those of slots j^1, j^2
-// and j^4.  A work-item so gathers 5 neighbour spinors from memory instead
 // of 8.  The projector signs depend on the site's offsets and are applied
 // per lane.  Order: inside x, then outside and inside directions
 // alternating, with two outside spinors in flight besides the one read from
