@@ -1629,9 +1629,9 @@ std::vector<int> site_order(const eofa_ctx* c, const Tiling& T, bool blocks = fa
         for (int d = 1; d < 4; ++d) if (ext[d] < 1) ext[d] = 1;
         int od[2], k = 0;   // the two non-sweep dims among y, z, t, slower one first
         for (int d = 3; d >= 1; --d) if (d != T.sweep) od[k++] = d;
-        for (int X = 0; X < 8; ++X) {
-            int r = X;
-            for (int d = 0; d < 4; ++d) {   // region of XCD X, x fastest
+        for (int xcd = 0; xcd < 8; ++xcd) {
+            int r = xcd;
+            for (int d = 0; d < 4; ++d) {   // region of this XCD, x fastest
                 const int w = E[d] / T.parts[d], i = r % T.parts[d];
                 r /= T.parts[d];
                 lo[d] = i * w;

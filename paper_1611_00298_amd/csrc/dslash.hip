@@ -28,7 +28,7 @@ namespace eofa {
 // (1 + sg gamma_mu) psi = (h ; sg A^dag h),  h = psi_up + sg A psi_lo.
 // ---------------------------------------------------------------------------
 template <int MU, typename A>
-__device__ __forceinline__ void project(const A (&p)[24], A SG, A (&h)[12]) {
+__device__ __forceinline__ void project(const A (&p)[24], A sg, A (&h)[12]) {
     // complex (spin k, colour c): re = p[2*(3k+c)], im = +1
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -37,17 +37,17 @@ __device__ __forceinline__ void project(const A (&p)[24], A SG, A (&h)[12]) {
         const A r2 = p[2 * (6 + c)], i2 = p[2 * (6 + c) + 1];
         const A r3 = p[2 * (9 + c)], i3 = p[2 * (9 + c) + 1];
         if constexpr (MU == 0) {        // A psi_lo = (-i psi3, -i psi2)
-            h[2 * c] = r0 + SG * i3;       h[2 * c + 1] = i0 - SG * r3;
-            h[6 + 2 * c] = r1 + SG * i2;   h[6 + 2 * c + 1] = i1 - SG * r2;
+            h[2 * c] = r0 + sg * i3;       h[2 * c + 1] = i0 - sg * r3;
+            h[6 + 2 * c] = r1 + sg * i2;   h[6 + 2 * c + 1] = i1 - sg * r2;
         } else if constexpr (MU == 1) { // A psi_lo = (-psi3, psi2)
-            h[2 * c] = r0 - SG * r3;       h[2 * c + 1] = i0 - SG * i3;
-            h[6 + 2 * c] = r1 + SG * r2;   h[6 + 2 * c + 1] = i1 + SG * i2;
+            h[2 * c] = r0 - sg * r3;       h[2 * c + 1] = i0 - sg * i3;
+            h[6 + 2 * c] = r1 + sg * r2;   h[6 + 2 * c + 1] = i1 + sg * i2;
         } else if constexpr (MU == 2) { // A psi_lo = (-i psi2, i psi3)
-            h[2 * c] = r0 + SG * i2;       h[2 * c + 1] = i0 - SG * r2;
-            h[6 + 2 * c] = r1 - SG * i3;   h[6 + 2 * c + 1] = i1 + SG * r3;
+            h[2 * c] = r0 + sg * i2;       h[2 * c + 1] = i0 - sg * r2;
+            h[6 + 2 * c] = r1 - sg * i3;   h[6 + 2 * c + 1] = i1 + sg * r3;
         } else {                        // A psi_lo = (psi2, psi3)
-            h[2 * c] = r0 + SG * r2;       h[2 * c + 1] = i0 + SG * i2;
-            h[6 + 2 * c] = r1 + SG * r3;   h[6 + 2 * c + 1] = i1 + SG * i3;
+            h[2 * c] = r0 + sg * r2;       h[2 * c + 1] = i0 + sg * i2;
+            h[6 + 2 * c] = r1 + sg * r3;   h[6 + 2 * c + 1] = i1 + sg * i3;
         }
     }
 }
@@ -55,7 +55,7 @@ __device__ __forceinline__ void project(const A (&p)[24], A SG, A (&h)[12]) {
 // acc_up += u ; acc_lo += sg A^dag u  (sg = +-1: a constant on the
 // fixed-direction paths, per lane on the block paths)
 template <int MU, typename A>
-__device__ __forceinline__ void reconstruct(const A (&u)[12], A SG, A (&acc)[24]) {
+__device__ __forceinline__ void reconstruct(const A (&u)[12], A sg, A (&acc)[24]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const A r0 = u[2 * c], i0 = u[2 * c + 1];
@@ -65,17 +65,17 @@ __device__ __forceinline__ void reconstruct(const A (&u)[12], A SG, A (&acc)[24]
         A* l2 = &acc[2 * (6 + c)];
         A* l3 = &acc[2 * (9 + c)];
         if constexpr (MU == 0) {        // A^dag u = (i u1, i u0)
-            l2[0] -= SG * i1; l2[1] += SG * r1;
-            l3[0] -= SG * i0; l3[1] += SG * r0;
+            l2[0] -= sg * i1; l2[1] += sg * r1;
+            l3[0] -= sg * i0; l3[1] += sg * r0;
         } else if constexpr (MU == 1) { // A^dag u = (u1, -u0)
-            l2[0] += SG * r1; l2[1] += SG * i1;
-            l3[0] -= SG * r0; l3[1] -= SG * i0;
+            l2[0] += sg * r1; l2[1] += sg * i1;
+            l3[0] -= sg * r0; l3[1] -= sg * i0;
         } else if constexpr (MU == 2) { // A^dag u = (i u0, -i u1)
-            l2[0] -= SG * i0; l2[1] += SG * r0;
-            l3[0] += SG * i1; l3[1] -= SG * r1;
+            l2[0] -= sg * i0; l2[1] += sg * r0;
+            l3[0] += sg * i1; l3[1] -= sg * r1;
         } else {                        // A^dag u = (u0, u1)
-            l2[0] += SG * r0; l2[1] += SG * i0;
-            l3[0] += SG * r1; l3[1] += SG * i1;
+            l2[0] += sg * r0; l2[1] += sg * i0;
+            l3[0] += sg * r1; l3[1] += sg * i1;
         }
     }
 }
