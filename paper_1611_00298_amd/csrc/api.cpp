@@ -196,8 +196,7 @@ struct eofa_ctx {
 namespace {
 
 enum Slot { S_WW = 0, S_ZZ0 = 1, S_ZZ1 = 2, S_RR = 3, S_B2 = 4, S_T0 = 5, S_T1 = 6, S_ALPHA = 8,
-            S_NSLOT = 16 };
-constexpr int XBATCH = 8;   // search directions per batched solution update
+            S_NSLOT = S_ALPHA + XBATCH };
 
 size_t half_bytes(const eofa_ctx* c, int prec) { return (size_t)16 * nblocks_of(prec) * c->N; }
 

@@ -78,9 +78,9 @@ __global__ void __launch_bounds__(256) k_r_update(void* r, float* rn, const void
 
 // x += sum_j alpha_j p_j over a batch of saved search directions
 struct PBatch {
-    const void* p[8];
-    const float* pn[8];
-    int slot[8];   // alpha_j = sc[slot[j]]
+    const void* p[XBATCH];
+    const float* pn[XBATCH];
+    int slot[XBATCH];   // alpha_j = sc[slot[j]]
     int cnt;
 };
 
@@ -89,15 +89,15 @@ __global__ void __launch_bounds__(256) k_x_batch(void* x, float* xn, const PBatc
                                                  size_t n5, size_t N) {
     using A = typename PT<P>::A;
     using AX = typename PT<PX>::A;
-    AX al[8];
+    AX al[XBATCH];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) al[j] = j < b.cnt ? (AX)sc[b.slot[j]] : AX(0);
+    for (int j = 0; j < XBATCH; ++j) al[j] = j < b.cnt ? (AX)sc[b.slot[j]] : AX(0);
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < n5;
          n += (size_t)gridDim.x * blockDim.x) {
         AX xv[24];
         ld_spinor<PX>(x, xn, N, n, xv);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < XBATCH; ++j) {
             if (j < b.cnt) {
                 A pv[24];
                 ld_spinor<P>(b.p[j], b.pn[j], N, n, pv);
@@ -301,9 +301,9 @@ hipError_t launch_r_update(int prec, void* r, float* rn, const void* w, const fl
 hipError_t launch_x_batch(int prec, void* x, float* xn, const void* const* p, const float* const* pn,
                           const int* slots, int cnt, const double* sc, size_t n5, size_t N, int nblk,
                           hipStream_t st) {
-    if (cnt < 1 || cnt > 8) return hipErrorInvalidValue;
+    if (cnt < 1 || cnt > XBATCH) return hipErrorInvalidValue;
     PBatch b;
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < XBATCH; ++j) {
         b.p[j] = j < cnt ? p[j] : nullptr;
         b.pn[j] = j < cnt ? pn[j] : nullptr;
         b.slot[j] = j < cnt ? slots[j] : 0;

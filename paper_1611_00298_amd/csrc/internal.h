@@ -203,6 +203,8 @@ constexpr int link_prec(int p) { return p == P64 ? P64 : P32; }
 // doubles: one partial sum per 256 links, so lattices of up to 2^20 4D
 // sites (128 KiB per GPU).
 constexpr int MD_SCRATCH_DOUBLES = 16384;
+// search directions per batched solution update (x += sum_j alpha_j p_j)
+constexpr int XBATCH = 16;
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumber them so that XCD x works on one contiguous range of
