@@ -26,6 +26,7 @@
 
 namespace eofa {
 hipError_t launch_hop(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st);
+int hop_occupancy(int prec, bool mfma, bool blk, int NS, int Ls);
 hipError_t launch_pupdate(int prec, const void* z, const float* zn, const void* po, const float* pon,
                           void* p, float* pn, void* pt,
                           float* ptn, const double* sc, int i_new, int i_old, int first, int Vh,
@@ -1794,11 +1795,18 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             if (const char* e = getenv("EOFA_MFMA_DEPTH")) c->mfma_depth = atoi(e);
             // block traversal (and block-sharing hops): the FP32 path and the
             // matrix-core paths, whenever a workgroup holds whole 2x2x2x2 blocks
+            // and the block form's extra LDS costs no workgroups per CU (at
+            // Ls = 8 the links of 24 sites per workgroup already fill it)
             bool blocks_ok = c->NS % 8 == 0;
             if (const char* e = getenv("EOFA_BLOCKS")) blocks_ok = blocks_ok && atoi(e) != 0;   // tuning
             const bool mf_ok = c->use_mfma && c->Ls % 4 == 0;
             for (int p = 0; p < 4; ++p) {
-                const bool blocks = blocks_ok && (p == P32 || (mf_ok && (p == P16 || p == PB16)));
+                bool blocks = blocks_ok && (p == P32 || (mf_ok && (p == P16 || p == PB16)));
+                if (blocks) {
+                    const bool mf = p != P32;
+                    const int with = hop_occupancy(p, mf, true, c->NS, c->Ls);
+                    blocks = with > 0 && with >= hop_occupancy(p, mf, false, c->NS, c->Ls);
+                }
                 const std::vector<int> ord = site_order(c, default_tiling(c, p, blocks), blocks);
                 c->blk[p] = blocks;
                 hipchk(hipMalloc((void**)&c->sites[p], sizeof(int) * ord.size()), "hipMalloc(site table)");

@@ -1188,6 +1188,32 @@ hipError_t launch_hop_dense(int prec, bool dag, bool hop, const HopArgs& a, int 
     return hipErrorInvalidValue;
 }
 
+// Workgroups per CU of the hop kernel (the K1 form: hop plus a column
+// sweep) in its per-site or block-sharing form, as the runtime's occupancy
+// calculator gives them for NS sites of Ls slices per workgroup; 0 on error.
+// The block form needs more LDS, which lowers the occupancy where the links
+// of many sites already fill it (small Ls).
+template <int P, int MF, bool BLK>
+static int hop_wg_per_cu(int NS, int Ls) {
+    using A = typename PT<P>::A;
+    const int NT = NS * Ls;
+    const size_t tile = (size_t)STR * NT * sizeof(A);
+    const size_t stage = stage_bytes(LinkLds<P, MF ? 1 : 0>::LB, NS);
+    const size_t shm = std::max(tile, stage + (BLK ? share_bytes(P, MF != 0, NT) : 0));
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_hop<P, false, true, MF, false, BLK>),
+                                                     NT, shm) != hipSuccess)
+        return 0;
+    return n;
+}
+
+int hop_occupancy(int prec, bool mfma, bool blk, int NS, int Ls) {
+    if (prec == P16 && mfma) return blk ? hop_wg_per_cu<P16, 3, true>(NS, Ls) : hop_wg_per_cu<P16, 3, false>(NS, Ls);
+    if (prec == PB16 && mfma) return blk ? hop_wg_per_cu<PB16, 3, true>(NS, Ls) : hop_wg_per_cu<PB16, 3, false>(NS, Ls);
+    if (prec == P32) return blk ? hop_wg_per_cu<P32, 0, true>(NS, Ls) : hop_wg_per_cu<P32, 0, false>(NS, Ls);
+    return 0;
+}
+
 hipError_t launch_hop(int prec, bool dag, bool hop, const HopArgs& a, int nblk, hipStream_t st) {
 #define EOFA_CASE(PP)                                                         \
     case PP:                                                                  \
