@@ -164,6 +164,7 @@ struct eofa_ctx {
     int* nbr = nullptr;
     int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
     int blk[4] = {0, 0, 0, 0};   // the table lists whole 2x2x2x2 blocks (FP32 and matrix-core paths)
+    int* nbrb[4] = {nullptr, nullptr, nullptr, nullptr};   // block-major neighbours of a block table
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
     void* frag = nullptr;        // compact FP16 links for the matrix-core FP16 hop (4 | Ls)
@@ -323,6 +324,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.par = h.par;
     const bool mfma = (h.prec == P16 || h.prec == PB16) && c->Ls % 4 == 0 && c->use_mfma;
     a.blk = (mfma || h.prec == P32) && h.hop && c->blk[h.prec];
+    if (a.blk) a.nbrb = c->nbrb[h.prec] + (size_t)h.par * 5 * c->nblk_hop * c->NS;
     if (h.hop && !mfma) {   // the matrix-core paths read only their compact 16-bit links
         const int lp = link_prec(h.prec);
         a.gauge = (const char*)gauge_of(c, lp) + (size_t)h.par * 8 * 9 * c->Vh * complex_bytes(lp);
@@ -1559,6 +1561,7 @@ void free_ctx(eofa_ctx* c) {
     for (int p = 0; p < 4; ++p) if (c->gauge[p]) (void)hipFree(c->gauge[p]);
     for (int p = 0; p < 4; ++p) if (c->sites[p]) (void)hipFree(c->sites[p]);
     if (c->nbr) (void)hipFree(c->nbr);
+    for (int p = 0; p < 4; ++p) if (c->nbrb[p]) (void)hipFree(c->nbrb[p]);
     if (c->U_nat) (void)hipFree(c->U_nat);
     if (c->frag) (void)hipFree(c->frag);
     if (c->frag_b) (void)hipFree(c->frag_b);
@@ -1669,6 +1672,40 @@ std::vector<int> site_order(const eofa_ctx* c, const Tiling& T, bool blocks = fa
     }
     ord.resize(nslot, Vh);   // padding slots are inactive
     return ord;
+}
+
+// Block-major neighbour table of a block traversal table `ord`: for output
+// parity p, block b of the table (slots 8b..8b+7) and k = 0..4, the
+// checkerboard index of slot j's neighbour along its inside direction x
+// (k = 0) and its outside direction mu = k - 1, at [p][b][k][j].  The 40
+// entries a workgroup's block reads are then 160 contiguous bytes instead of
+// 40 scattered rows of the per-direction table.  Padding slots get 0.
+std::vector<int> block_neighbours(const eofa_ctx* c, const std::vector<int>& ord) {
+    const int nb = (int)ord.size() / 8;
+    std::vector<int> out((size_t)2 * nb * 40, 0);
+    for (int p = 0; p < 2; ++p)
+        for (int b = 0; b < nb; ++b)
+            for (int j = 0; j < 8; ++j) {
+                const int cb = ord[8 * b + j];
+                if (cb >= c->Vh) continue;
+                int x[4];
+                int r = 2 * cb;
+                x[0] = r % c->L[0]; r /= c->L[0];
+                x[1] = r % c->L[1]; r /= c->L[1];
+                x[2] = r % c->L[2]; x[3] = r / c->L[2];
+                x[0] += (p + x[1] + x[2] + x[3]) & 1;
+                const int off = (j << 1) | ((__builtin_popcount(j) + p) & 1);
+                for (int k = 0; k < 5; ++k) {
+                    const int mu = k == 0 ? 0 : k - 1;
+                    const bool fwd_inside = ((off >> mu) & 1) == 0;   // +mu lies inside the block
+                    const bool fwd = k == 0 ? fwd_inside : !fwd_inside;
+                    int e[4] = {x[0], x[1], x[2], x[3]};
+                    e[mu] = (e[mu] + (fwd ? 1 : c->L[mu] - 1)) % c->L[mu];
+                    const int i = e[0] + c->L[0] * (e[1] + c->L[1] * (e[2] + c->L[2] * e[3]));
+                    out[(((size_t)p * nb + b) * 5 + k) * 8 + j] = i >> 1;
+                }
+            }
+    return out;
 }
 
 // Default tiling per precision (measured at 24^3x64, Ls = 24, and in a
@@ -1809,6 +1846,12 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
                 }
                 const std::vector<int> ord = site_order(c, default_tiling(c, p, blocks), blocks);
                 c->blk[p] = blocks;
+                if (blocks) {
+                    const std::vector<int> nbb = block_neighbours(c, ord);
+                    hipchk(hipMalloc((void**)&c->nbrb[p], sizeof(int) * nbb.size()), "hipMalloc(block neighbours)");
+                    hipchk(hipMemcpy(c->nbrb[p], nbb.data(), sizeof(int) * nbb.size(), hipMemcpyHostToDevice),
+                           "copy block neighbours");
+                }
                 hipchk(hipMalloc((void**)&c->sites[p], sizeof(int) * ord.size()), "hipMalloc(site table)");
                 hipchk(hipMemcpy(c->sites[p], ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice),
                        "copy site table");

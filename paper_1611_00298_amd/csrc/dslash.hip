@@ -296,7 +296,7 @@ __host__ __device__ constexpr size_t share_bytes(int P, bool mf, int NT) {
 // LDS per workgroup, one workgroup per CU fewer than the per-site form, which
 // cancels the gain (measured 1.76-1.77 against 1.75 ms at 24^3x64, Ls = 24).
 template <int P, bool DAG>
-__device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned char* lds, int site, int sl, int s,
+__device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned char* lds, int sl, int s,
                                             typename PT<P>::A (&acc)[24]) {
     using A = typename PT<P>::A;
     constexpr int LB = LinkLds<P, 0>::LB;
@@ -307,7 +307,8 @@ __device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned c
     const int off = (j << 1) | ((__popc(j) + a.par) & 1);   // b_x + 2 b_y + 4 b_z + 8 b_t
     auto din = [&](int mu) { return mu + 4 * ((off >> mu) & 1); };
     auto sgn = [&](int d) { return (A)((d < 4 ? -1 : 1) * (DAG ? -1 : 1)); };
-    auto nbr_of = [&](int d) { return a.nbr[(size_t)d * a.Vh + site]; };
+    // neighbour indices from the block-major table: x inside, then the outside ones
+    const int* nb = a.nbrb + ((size_t)(lb * (a.NS >> 3) + (sl >> 3)) * 5) * 8 + j;
     uint4* sh = reinterpret_cast<uint4*>(lds + stage_bytes(LB, a.NS));
     auto put = [&](const Stage<P>& st) {
 #pragma unroll
@@ -344,9 +345,9 @@ __device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned c
     };
     int nbo[4];
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) nbo[mu] = nbr_of(din(mu) ^ 4);
+    for (int mu = 0; mu < 4; ++mu) nbo[mu] = nb[8 * (mu + 1)];
     Stage<P> sx, o[2];
-    load_stage<P>(a, s, nbr_of(din(0)), sx);
+    load_stage<P>(a, s, nb[0], sx);
     load_stage<P>(a, s, nbo[0], o[0]);
     load_stage<P>(a, s, nbo[1], o[1]);
     stage_links<P, 0>(a, lb, lds);
@@ -607,7 +608,7 @@ __device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int lb, unsigned 
 // alternating, with two outside spinors in flight besides the one read from
 // LDS (the register budget of the 5-wave FP16 kernel).
 template <int P, bool DAG>
-__device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned char* lds, int site, int sl, int s,
+__device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned char* lds, int sl, int s,
                                              int lane4, float (&acc)[24]) {
     constexpr int LB = LinkLds<P, 1>::LB;
     const int tid = threadIdx.x, NT = blockDim.x;
@@ -617,11 +618,12 @@ __device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned 
     // mu + 4 (backward, +1) if b_mu = 1; the outside direction is the other
     auto din = [&](int mu) { return mu + 4 * ((off >> mu) & 1); };
     auto sgn = [&](int d) { return (d < 4 ? -1.f : 1.f) * (DAG ? -1.f : 1.f); };
-    auto nbr_of = [&](int d) { return a.nbr[(size_t)d * a.Vh + site]; };
-    const int nbx = nbr_of(din(0));
+    // neighbour indices from the block-major table: x inside, then the outside ones
+    const int* nb = a.nbrb + ((size_t)(lb * (a.NS >> 3) + (sl >> 3)) * 5) * 8 + j;
+    const int nbx = nb[0];
     int nbo[4];
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) nbo[mu] = nbr_of(din(mu) ^ 4);
+    for (int mu = 0; mu < 4; ++mu) nbo[mu] = nb[8 * (mu + 1)];
     MStage sx, o[2];
     load_mstage<P>(a, s, nbx, sx);
     load_mstage<P>(a, s, nbo[0], o[0]);
@@ -914,9 +916,9 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) 
             stage_links<P, 0>(a, lb, smem_raw);
             __syncthreads();
         }
-        if constexpr (MF && BLK) hop_blk_mfma<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
+        if constexpr (MF && BLK) hop_blk_mfma<P, DAG>(a, lb, smem_raw, sl, s, tid & 3, v);
         else if constexpr (MF) hop_all_mfma<P, DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
-        else if constexpr (BLK) hop_blk_vec<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
+        else if constexpr (BLK) hop_blk_vec<P, DAG>(a, lb, smem_raw, sl, s, v);
         else if constexpr (P == P64) { if (active) hop_all<P, DAG>(a, lb, smem_raw, site, sl, s, v); }
         else hop_all<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
         if (!active) {

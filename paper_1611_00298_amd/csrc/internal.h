@@ -271,7 +271,8 @@ struct HopArgs {
     const void* frag;    // compact FP16 links for the matrix-core path, [8][Vh][9] (re, im) halves (nullable)
     int depth;           // directions of operands kept in flight (matrix-core path)
     int par;             // parity of the output sites
-    int blk;             // matrix-core path: the site table lists whole 2x2x2x2 blocks, 8 slots each
+    int blk;             // the site table lists whole 2x2x2x2 blocks, 8 slots each (block-sharing hops)
+    const int* nbrb;     // with blk: neighbours of the table's blocks, [block][k][slot] (k = 0: x inside, 1-4: outside)
     int Vh, Ls, NS;
     size_t N;
     double mp, mm;
