@@ -51,6 +51,8 @@ hipError_t launch_ingest_gauge(const void* U, void* G, int* nbr, const int L[4],
                                hipStream_t st);
 hipError_t launch_gauge_convert(int po, const void* in, void* out, size_t n, hipStream_t st);
 hipError_t launch_gauge_c16(const void* in, void* out, int Vh, int bf, hipStream_t st);
+hipError_t launch_links_blocked(const void* src, void* dst, const int* sites, int Vh, int nslot, int wide,
+                                hipStream_t st);
 hipError_t launch_nat5_to_dev(const void* nat, void* de, void* dodd, const int L[4], int Ls, size_t N,
                               hipStream_t st);
 hipError_t launch_dev_to_nat5(void* nat, const void* de, const void* dodd, const int L[4], int Ls,
@@ -165,6 +167,7 @@ struct eofa_ctx {
     int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
     int blk[4] = {0, 0, 0, 0};   // the table lists whole 2x2x2x2 blocks (FP32 and matrix-core paths)
     int* nbrb[4] = {nullptr, nullptr, nullptr, nullptr};   // block-major neighbours of a block table
+    void* lnkb[4] = {nullptr, nullptr, nullptr, nullptr};  // block-major links of a block table (P32, P16, PB16)
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
     void* frag = nullptr;        // compact FP16 links for the matrix-core FP16 hop (4 | Ls)
@@ -232,6 +235,16 @@ void* gauge_of(eofa_ctx* c, int prec) {
         hipchk(launch_gauge_convert(prec, c->gauge[P64], c->gauge[prec], nc, c->st), "gauge convert");
     }
     return c->gauge[prec];
+}
+
+// Block-major links of precision p's block table (FP32 links, or the compact
+// 16-bit links of the matrix-core paths), rebuilt whenever the links change.
+constexpr size_t link_record_bytes(int p) { return p == P32 ? 72 : 36; }
+
+void build_links_blocked(eofa_ctx* c, int p) {
+    const void* src = p == P32 ? gauge_of(c, P32) : (p == PB16 ? c->frag_b : c->frag);
+    hipchk(launch_links_blocked(src, c->lnkb[p], c->sites[p], c->Vh, c->nblk_hop * c->NS, p == P32, c->st),
+           "block-major links");
 }
 
 // ---- timing ---------------------------------------------------------------
@@ -338,6 +351,14 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
         }
         a.frag = (const char*)fr + (size_t)h.par * 8 * c->Vh * 36;
         a.depth = c->mfma_depth;
+    }
+    if (a.blk) {   // the block-sharing hops stage their links from the block-major copy
+        const size_t per_par = (size_t)c->nblk_hop * c->NS * 8 * link_record_bytes(h.prec);
+        if (!c->lnkb[h.prec]) {
+            hipchk(hipMalloc(&c->lnkb[h.prec], 2 * per_par), "hipMalloc(block-major links)");
+            build_links_blocked(c, h.prec);
+        }
+        a.lnkb = (const char*)c->lnkb[h.prec] + (size_t)h.par * per_par;
     }
     a.Vh = c->Vh;
     a.Ls = c->Ls;
@@ -1562,6 +1583,7 @@ void free_ctx(eofa_ctx* c) {
     for (int p = 0; p < 4; ++p) if (c->sites[p]) (void)hipFree(c->sites[p]);
     if (c->nbr) (void)hipFree(c->nbr);
     for (int p = 0; p < 4; ++p) if (c->nbrb[p]) (void)hipFree(c->nbrb[p]);
+    for (int p = 0; p < 4; ++p) if (c->lnkb[p]) (void)hipFree(c->lnkb[p]);
     if (c->U_nat) (void)hipFree(c->U_nat);
     if (c->frag) (void)hipFree(c->frag);
     if (c->frag_b) (void)hipFree(c->frag_b);
@@ -1759,6 +1781,8 @@ void load_gauge(eofa_ctx* c, const void* U) {
         if (c->gauge[p]) hipchk(launch_gauge_convert(p, c->gauge[P64], c->gauge[p], nc, c->st), "gauge convert");
     if (c->frag) hipchk(launch_gauge_c16(c->gauge[P64], c->frag, c->Vh, 0, c->st), "FP16 links");
     if (c->frag_b) hipchk(launch_gauge_c16(c->gauge[P64], c->frag_b, c->Vh, 1, c->st), "BF16 links");
+    for (int p : {P32, P16, PB16})
+        if (c->lnkb[p]) build_links_blocked(c, p);
 }
 
 }  // namespace

@@ -182,6 +182,44 @@ __device__ __forceinline__ void stage_links(const HopArgs& a, int lb, unsigned c
     }
 }
 
+// The same staging for the block-sharing hops, from the block-major copy of
+// the links (a.lnkb: the 64 records of a block contiguous, record (d, j) of
+// 36 B compact 16-bit or 72 B FP32 links), so that a workgroup's link loads
+// cover a few whole cache lines instead of one partial line per record.
+// Consecutive work-items read consecutive words.
+template <int P, int MF>
+__device__ __forceinline__ void stage_links_blk(const HopArgs& a, int lb, unsigned char* lds) {
+    constexpr int LB = LinkLds<P, MF>::LB;
+    const int NS = a.NS, NT = blockDim.x, tid = threadIdx.x;
+    const size_t blk0 = (size_t)lb * (NS >> 3);   // first block of the workgroup
+    if constexpr (MF != 0) {
+        // as stage_links: row r of the real 6x6 form from 3 words of the record
+        const uint32_t* g = reinterpret_cast<const uint32_t*>(a.lnkb) + blk0 * 64 * 9;
+        for (int e = tid; e < NS * 64; e += NT) {
+            const int r = e & 7, q = e >> 3;   // q = (block, d, slot) record index in the workgroup
+            const int jj = q & 7, d = (q >> 3) & 7, j = ((q >> 6) << 3) + jj;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (r < 6) {
+                const uint32_t* w = g + (size_t)q * 9 + 3 * (r >> 1);
+                const uint32_t w0 = __builtin_nontemporal_load(w), w1 = __builtin_nontemporal_load(w + 1),
+                               w2 = __builtin_nontemporal_load(w + 2);   // read once per launch
+                if (r & 1) v = make_uint4(__builtin_amdgcn_alignbit(w0, w0, 16), __builtin_amdgcn_alignbit(w1, w1, 16),
+                                          __builtin_amdgcn_alignbit(w2, w2, 16), 0u);
+                else v = make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
+            }
+            *reinterpret_cast<uint4*>(lds + (j * 8 + d) * LB + 16 * r) = v;
+        }
+    } else {
+        static_assert(P == P32, "the vector block path stages FP32 links");
+        const float2* g = reinterpret_cast<const float2*>(a.lnkb) + blk0 * 64 * 9;
+        for (int e = tid; e < NS * 72; e += NT) {
+            const int q = e / 9, k = e - 9 * q;
+            const int jj = q & 7, d = (q >> 3) & 7, j = ((q >> 6) << 3) + jj;
+            *reinterpret_cast<float2*>(lds + (j * 8 + d) * LB + 8 * k) = g[e];
+        }
+    }
+}
+
 // One direction's neighbour spinor, loaded ahead of its use.
 template <int P> struct Stage {
     using A = typename PT<P>::A;
@@ -350,7 +388,7 @@ __device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned c
     load_stage<P>(a, s, nb[0], sx);
     load_stage<P>(a, s, nbo[0], o[0]);
     load_stage<P>(a, s, nbo[1], o[1]);
-    stage_links<P, 0>(a, lb, lds);
+    stage_links_blk<P, 0>(a, lb, lds);
     put(sx);
     __syncthreads();
     compute_stage_sg<P, 0>(sx, lr + din(0) * LB, sgn(din(0)), acc);
@@ -628,7 +666,7 @@ __device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned 
     load_mstage<P>(a, s, nbx, sx);
     load_mstage<P>(a, s, nbo[0], o[0]);
     load_mstage<P>(a, s, nbo[1], o[1]);
-    stage_links<P, 1>(a, lb, lds);
+    stage_links_blk<P, 1>(a, lb, lds);
     uint4* sh = reinterpret_cast<uint4*>(lds + stage_bytes(LB, a.NS));
     float* shn = reinterpret_cast<float*>(sh + 3 * NT);
 #pragma unroll

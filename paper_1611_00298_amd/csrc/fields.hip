@@ -334,6 +334,38 @@ hipError_t launch_hb_accum(void* phi, const void* ce, const void* co, const doub
     return hipGetLastError();
 }
 
+// Links of a block traversal table in block-major order, for the
+// block-sharing hops: record (p, b, d, j) = the link of direction d of the
+// site in slot j of block b (sites[8 b + j]) for output parity p, the 8
+// direction records of a block's 8 slots contiguous.  16-bit compact links
+// (wide = 0): source [p][d][Vh][9] words, 36 B records; FP32 links (wide =
+// 1): source [p][d][9][Vh] complex, 72 B records.  Padding slots get zeros.
+// One work-item per record.
+__global__ void k_links_blocked(const void* __restrict__ src, void* __restrict__ dst,
+                                const int* __restrict__ sites, int Vh, int nblk, int wide) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * nblk * 64) return;
+    const int j = t & 7, d = (t >> 3) & 7, pb = t >> 6;
+    const int p = pb / nblk, b = pb - p * nblk;
+    const int site = sites[8 * b + j];
+    if (wide) {
+        const float2* in = reinterpret_cast<const float2*>(src) + ((size_t)p * 8 + d) * 9 * Vh;
+        float2* out = reinterpret_cast<float2*>(dst) + (size_t)t * 9;
+        for (int k = 0; k < 9; ++k) out[k] = site < Vh ? in[(size_t)k * Vh + site] : make_float2(0.f, 0.f);
+    } else {
+        const uint32_t* in = reinterpret_cast<const uint32_t*>(src) + (((size_t)p * 8 + d) * Vh + site) * 9;
+        uint32_t* out = reinterpret_cast<uint32_t*>(dst) + (size_t)t * 9;
+        for (int k = 0; k < 9; ++k) out[k] = site < Vh ? in[k] : 0u;
+    }
+}
+
+hipError_t launch_links_blocked(const void* src, void* dst, const int* sites, int Vh, int nslot, int wide,
+                                hipStream_t st) {
+    const int nblk = nslot / 8, n = 2 * nblk * 64;
+    hipLaunchKernelGGL(k_links_blocked, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, sites, Vh, nblk, wide);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauge_c16(const void* in, void* out, int Vh, int bf, hipStream_t st) {
     const int n = 2 * 8 * Vh;
     hipLaunchKernelGGL(k_gauge_c16, dim3((n + 255) / 256), dim3(256), 0, st, (const double2*)in, (uint32_t*)out, Vh,

@@ -273,6 +273,7 @@ struct HopArgs {
     int par;             // parity of the output sites
     int blk;             // the site table lists whole 2x2x2x2 blocks, 8 slots each (block-sharing hops)
     const int* nbrb;     // with blk: neighbours of the table's blocks, [block][k][slot] (k = 0: x inside, 1-4: outside)
+    const void* lnkb;    // with blk: the links in block-major order, [block][d][slot] records (FP32 or compact 16-bit)
     int Vh, Ls, NS;
     size_t N;
     double mp, mm;
