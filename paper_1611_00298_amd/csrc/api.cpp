@@ -167,6 +167,7 @@ struct eofa_ctx {
     int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
     int blk[4] = {0, 0, 0, 0};   // the table lists whole 2x2x2x2 blocks (FP32 and matrix-core paths)
     int* nbrb[4] = {nullptr, nullptr, nullptr, nullptr};   // block-major neighbours of a block table
+    int* fsites = nullptr;   // the force kernel's traversal (the FP64 per-site table)
     void* lnkb[4] = {nullptr, nullptr, nullptr, nullptr};  // block-major links of a block table (P32, P16, PB16)
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
@@ -239,11 +240,12 @@ void* gauge_of(eofa_ctx* c, int prec) {
 
 // Block-major links of precision p's block table (FP32 links, or the compact
 // 16-bit links of the matrix-core paths), rebuilt whenever the links change.
-constexpr size_t link_record_bytes(int p) { return p == P32 ? 72 : 36; }
+constexpr size_t link_record_bytes(int p) { return p == P64 ? 144 : p == P32 ? 72 : 36; }
 
 void build_links_blocked(eofa_ctx* c, int p) {
-    const void* src = p == P32 ? gauge_of(c, P32) : (p == PB16 ? c->frag_b : c->frag);
-    hipchk(launch_links_blocked(src, c->lnkb[p], c->sites[p], c->Vh, c->nblk_hop * c->NS, p == P32, c->st),
+    const void* src = p == P64 ? c->gauge[P64] : p == P32 ? gauge_of(c, P32) : (p == PB16 ? c->frag_b : c->frag);
+    const int wide = p == P64 ? 2 : p == P32 ? 1 : 0;
+    hipchk(launch_links_blocked(src, c->lnkb[p], c->sites[p], c->Vh, c->nblk_hop * c->NS, wide, c->st),
            "block-major links");
 }
 
@@ -336,7 +338,7 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     a.sites = c->sites[h.prec];
     a.par = h.par;
     const bool mfma = (h.prec == P16 || h.prec == PB16) && c->Ls % 4 == 0 && c->use_mfma;
-    a.blk = (mfma || h.prec == P32) && h.hop && c->blk[h.prec];
+    a.blk = (mfma || h.prec == P64 || h.prec == P32) && h.hop && c->blk[h.prec];
     if (a.blk) a.nbrb = c->nbrb[h.prec] + (size_t)h.par * 5 * c->nblk_hop * c->NS;
     if (h.hop && !mfma) {   // the matrix-core paths read only their compact 16-bit links
         const int lp = link_prec(h.prec);
@@ -1583,6 +1585,7 @@ void free_ctx(eofa_ctx* c) {
     for (int p = 0; p < 4; ++p) if (c->sites[p]) (void)hipFree(c->sites[p]);
     if (c->nbr) (void)hipFree(c->nbr);
     for (int p = 0; p < 4; ++p) if (c->nbrb[p]) (void)hipFree(c->nbrb[p]);
+    if (c->fsites) (void)hipFree(c->fsites);
     for (int p = 0; p < 4; ++p) if (c->lnkb[p]) (void)hipFree(c->lnkb[p]);
     if (c->U_nat) (void)hipFree(c->U_nat);
     if (c->frag) (void)hipFree(c->frag);
@@ -1781,7 +1784,7 @@ void load_gauge(eofa_ctx* c, const void* U) {
         if (c->gauge[p]) hipchk(launch_gauge_convert(p, c->gauge[P64], c->gauge[p], nc, c->st), "gauge convert");
     if (c->frag) hipchk(launch_gauge_c16(c->gauge[P64], c->frag, c->Vh, 0, c->st), "FP16 links");
     if (c->frag_b) hipchk(launch_gauge_c16(c->gauge[P64], c->frag_b, c->Vh, 1, c->st), "BF16 links");
-    for (int p : {P32, P16, PB16})
+    for (int p : {P64, P32, P16, PB16})
         if (c->lnkb[p]) build_links_blocked(c, p);
 }
 
@@ -1859,17 +1862,27 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
             // and the block form's extra LDS costs no workgroups per CU (at
             // Ls = 8 the links of 24 sites per workgroup already fill it)
             bool blocks_ok = c->NS % 8 == 0;
-            if (const char* e = getenv("EOFA_BLOCKS")) blocks_ok = blocks_ok && atoi(e) != 0;   // tuning
+            int blocks_env = 1;
+            if (const char* e = getenv("EOFA_BLOCKS")) blocks_env = atoi(e);   // tuning: 0 off, 2 forced
+            blocks_ok = blocks_ok && blocks_env != 0;
             const bool mf_ok = c->use_mfma && c->Ls % 4 == 0;
             for (int p = 0; p < 4; ++p) {
-                bool blocks = blocks_ok && (p == P32 || (mf_ok && (p == P16 || p == PB16)));
-                if (blocks) {
-                    const bool mf = p != P32;
+                // (FP64: one link element per staging work-item needs Ls >= 18)
+                bool blocks = blocks_ok && (p == P32 || (p == P64 && c->Ls >= 18) ||
+                                            (mf_ok && (p == P16 || p == PB16)));
+                if (blocks && blocks_env != 2) {
+                    const bool mf = p == P16 || p == PB16;
                     const int with = hop_occupancy(p, mf, true, c->NS, c->Ls);
                     blocks = with > 0 && with >= hop_occupancy(p, mf, false, c->NS, c->Ls);
                 }
                 const std::vector<int> ord = site_order(c, default_tiling(c, p, blocks), blocks);
                 c->blk[p] = blocks;
+                if (p == P64) {   // the force kernel keeps the per-site order (faster for it)
+                    const std::vector<int> fo = blocks ? site_order(c, default_tiling(c, P64, false), false) : ord;
+                    hipchk(hipMalloc((void**)&c->fsites, sizeof(int) * fo.size()), "hipMalloc(force table)");
+                    hipchk(hipMemcpy(c->fsites, fo.data(), sizeof(int) * fo.size(), hipMemcpyHostToDevice),
+                           "copy force table");
+                }
                 if (blocks) {
                     const std::vector<int> nbb = block_neighbours(c, ord);
                     hipchk(hipMalloc((void**)&c->nbrb[p], sizeof(int) * nbb.size()), "hipMalloc(block neighbours)");
@@ -2037,7 +2050,7 @@ int eofa_force(eofa_ctx_t* c, double m1, double m2, const void* phi, const void*
         hipchk(launch_nat5_to_dev(chiL, le.d, lo.d, c->L, c->Ls, c->N, c->st), "layout");
         hipchk(launch_nat5_to_dev(chiR, re.d, ro.d, c->L, c->Ls, c->N, c->st), "layout");
         const int ev = timing_begin(c);
-        hipchk(launch_force(c->U_nat, le.d, lo.d, re.d, ro.d, c->nbr, c->sites[P64], k, F, G, c->L, c->Ls,
+        hipchk(launch_force(c->U_nat, le.d, lo.d, re.d, ro.d, c->nbr, c->fsites, k, F, G, c->L, c->Ls,
                             c->aperiodic, c->NS, c->nblk_hop, c->N, c->st), "force");
         // algorithmic bytes: chi_L and chi_R once, U, F (and G)
         timing_end(c, ev, C_FORCE, 2.0 * c->V * c->Ls * 192.0 + 4.0 * c->V * 144.0 * (G ? 3.0 : 2.0));

@@ -210,7 +210,7 @@ __device__ __forceinline__ void stage_links_blk(const HopArgs& a, int lb, unsign
             *reinterpret_cast<uint4*>(lds + (j * 8 + d) * LB + 16 * r) = v;
         }
     } else {
-        static_assert(P == P32, "the vector block path stages FP32 links");
+        static_assert(P == P32, "the vector block path stages FP32 links (FP64: hop_blk_f64)");
         const float2* g = reinterpret_cast<const float2*>(a.lnkb) + blk0 * 64 * 9;
         for (int e = tid; e < NS * 72; e += NT) {
             const int q = e / 9, k = e - 9 * q;
@@ -329,10 +329,8 @@ __host__ __device__ constexpr size_t share_bytes(int P, bool mf, int NT) {
 // along x (the block's opposite-parity site in the same slot) and shares it
 // through LDS, where the inside neighbours along y, z and t are those of
 // slots j^1, j^2 and j^4; the four outside neighbours come from memory, two
-// in flight.  5 gathers per work-item instead of 8.  Used for FP32: in FP64
-// the shared spinors (192 B per work-item) and the FP64 links need 46 KB of
-// LDS per workgroup, one workgroup per CU fewer than the per-site form, which
-// cancels the gain (measured 1.76-1.77 against 1.75 ms at 24^3x64, Ls = 24).
+// in flight.  5 gathers per work-item instead of 8.  Used for FP32 (FP64:
+// hop_blk_f64, which stages its links in phases to keep 4 workgroups per CU).
 template <int P, bool DAG>
 __device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned char* lds, int sl, int s,
                                             typename PT<P>::A (&acc)[24]) {
@@ -401,6 +399,97 @@ __device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned c
     outside(I2{}, o[0]);
     inside(I3{}, sx);
     outside(I3{}, o[1]);
+}
+
+// The FP64 block form.  Its shared spinors take 36.9 KB of LDS at 192
+// work-items, so the links are staged one phase (two directions per site)
+// at a time, 2.3 KB from the phase-ordered block-major copy, which keeps the
+// workgroup within 40 KB: 4 workgroups per CU as in the per-site form.
+// Phases: the inside x and y, the inside z and t (the shared spinors from
+// LDS), the outside x and y, the outside z and t (from memory), each
+// direction's operands one at a time (the registers hold one FP64 spinor
+// besides the accumulator).  Requires 18 NS <= NS Ls, one link element
+// per staging work-item.
+template <bool DAG>
+__device__ __forceinline__ void hop_blk_f64(const HopArgs& a, int lb, unsigned char* lds, int sl, int s,
+                                            double (&acc)[24]) {
+    constexpr int P = P64;
+    constexpr int LB = LinkLds<P, 0>::LB;
+    const int tid = threadIdx.x, NT = blockDim.x, NS = a.NS;
+    const int j = sl & 7;
+    const int off = (j << 1) | ((__popc(j) + a.par) & 1);   // b_x + 2 b_y + 4 b_z + 8 b_t
+    // direction of phase ph, slot k: phases 0, 1 the inside directions of
+    // mu = 2 (ph mod 2) + k, phases 2, 3 the outside ones
+    auto dir = [&](int ph, int k) {
+        const int mu = 2 * (ph & 1) + k;
+        const int d = mu + 4 * ((off >> mu) & 1);
+        return ph < 2 ? d : d ^ 4;
+    };
+    auto sgn = [](int d) { return (double)((d < 4 ? -1 : 1) * (DAG ? -1 : 1)); };
+    const int* nb = a.nbrb + ((size_t)(lb * (NS >> 3) + (sl >> 3)) * 5) * 8 + j;
+    uint4* sh = reinterpret_cast<uint4*>(lds);
+    unsigned char* lk = lds + share_bytes(P, false, NT);   // [NS][2] records of the phase, then 1 spare
+    // staging element of this work-item: complex eq of the record of slot ek
+    // of site ej; work-items beyond the NS*18 elements fetch site 0's and
+    // store to the spare record (a branch here would split the kernel's
+    // register ranges)
+    const bool stager = tid < NS * 18;
+    const int ej = stager ? tid / 18 : 0, ek = (tid / 9) & 1, eq = tid % 9;
+    const double2* lsrc = reinterpret_cast<const double2*>(a.lnkb) +
+                          (((size_t)lb * (NS >> 3) + (ej >> 3)) * 64 + ek * 8 + (ej & 7)) * 9 + eq;
+    const int erec = stager ? ej * 2 + ek : NS * 2;
+    auto fetch = [&](int ph) { return lsrc[(size_t)ph * 16 * 9]; };
+    auto store = [&](double2 v) { *reinterpret_cast<double2*>(lk + erec * LB + 16 * eq) = v; };
+    auto share = [&](const Stage<P>& st) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+            sh[c * NT + tid] = __builtin_bit_cast(uint4, make_double2(st.psi[2 * c], st.psi[2 * c + 1]));
+    };
+    auto get = [&](int src, Stage<P>& st) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double2 w = __builtin_bit_cast(double2, sh[c * NT + src]);
+            st.psi[2 * c] = w.x;
+            st.psi[2 * c + 1] = w.y;
+        }
+    };
+    auto next_phase = [&](int ph) {   // every work-item; the previous phase's records are read
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+        store(fetch(ph));
+        __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    const unsigned char* l0 = lk + sl * 2 * LB;
+    const unsigned char* l1 = l0 + LB;
+    Stage<P> st;
+    // phase 0: inside x (this work-item's load, shared) and inside y
+    load_stage<P>(a, s, nb[0], st);
+    share(st);
+    store(fetch(0));
+    __syncthreads();
+    compute_stage_sg<P, 0>(st, l0, sgn(dir(0, 0)), acc);
+    __builtin_amdgcn_sched_barrier(0);
+    get((sl ^ 1) * a.Ls + s, st);
+    compute_stage_sg<P, 1>(st, l1, sgn(dir(0, 1)), acc);
+    next_phase(1);   // inside z and t
+    get((sl ^ 2) * a.Ls + s, st);
+    compute_stage_sg<P, 2>(st, l0, sgn(dir(1, 0)), acc);
+    __builtin_amdgcn_sched_barrier(0);
+    get((sl ^ 4) * a.Ls + s, st);
+    compute_stage_sg<P, 3>(st, l1, sgn(dir(1, 1)), acc);
+    next_phase(2);   // outside x and y
+    load_stage<P>(a, s, nb[8], st);
+    compute_stage_sg<P, 0>(st, l0, sgn(dir(2, 0)), acc);
+    __builtin_amdgcn_sched_barrier(0);
+    load_stage<P>(a, s, nb[16], st);
+    compute_stage_sg<P, 1>(st, l1, sgn(dir(2, 1)), acc);
+    next_phase(3);   // outside z and t
+    load_stage<P>(a, s, nb[24], st);
+    compute_stage_sg<P, 2>(st, l0, sgn(dir(3, 0)), acc);
+    __builtin_amdgcn_sched_barrier(0);
+    load_stage<P>(a, s, nb[32], st);
+    compute_stage_sg<P, 3>(st, l1, sgn(dir(3, 1)), acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -950,12 +1039,13 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) 
     if (HOP) {
         // every work-item takes part (staging barrier; the MFMA needs the
         // whole wave); padding work-items read site 0 and discard it
-        if constexpr (P == P64) {
+        if constexpr (P == P64 && !BLK) {
             stage_links<P, 0>(a, lb, smem_raw);
             __syncthreads();
         }
         if constexpr (MF && BLK) hop_blk_mfma<P, DAG>(a, lb, smem_raw, sl, s, tid & 3, v);
         else if constexpr (MF) hop_all_mfma<P, DAG, MF>(a, lb, smem_raw, active ? site : 0, sl, s, tid & 3, v);
+        else if constexpr (BLK && P == P64) hop_blk_f64<DAG>(a, lb, smem_raw, sl, s, v);
         else if constexpr (BLK) hop_blk_vec<P, DAG>(a, lb, smem_raw, sl, s, v);
         else if constexpr (P == P64) { if (active) hop_all<P, DAG>(a, lb, smem_raw, site, sl, s, v); }
         else hop_all<P, DAG>(a, lb, smem_raw, active ? site : 0, sl, s, v);
@@ -1175,9 +1265,11 @@ static hipError_t launch_hop_t(const HopArgs& a, int nblk, hipStream_t st) {
             return hipGetLastError();
         }
     }
-    if constexpr (P == P32 && HOP) {
-        if (a.blk) {
-            const size_t shm = std::max(tile, stage_bytes(LinkLds<P, 0>::LB, a.NS) + share_bytes(P, false, NT));
+    if constexpr ((P == P64 || P == P32) && HOP) {
+        if (a.blk) {   // FP64: the shared spinors, then one phase's links and a spare record
+            const size_t links = P == P64 ? (size_t)(2 * a.NS + 1) * LinkLds<P, 0>::LB
+                                          : stage_bytes(LinkLds<P, 0>::LB, a.NS);
+            const size_t shm = std::max(tile, links + share_bytes(P, false, NT));
             hipLaunchKernelGGL((k_hop<P, DAG, HOP, 0, false, true>), dim3(nblk), dim3(NT), shm, st, a);
             return hipGetLastError();
         }
@@ -1238,7 +1330,8 @@ static int hop_wg_per_cu(int NS, int Ls) {
     using A = typename PT<P>::A;
     const int NT = NS * Ls;
     const size_t tile = (size_t)STR * NT * sizeof(A);
-    const size_t stage = stage_bytes(LinkLds<P, MF ? 1 : 0>::LB, NS);
+    const size_t stage = (BLK && P == P64) ? (size_t)(2 * NS + 1) * LinkLds<P, 0>::LB
+                                           : stage_bytes(LinkLds<P, MF ? 1 : 0>::LB, NS);
     const size_t shm = std::max(tile, stage + (BLK ? share_bytes(P, MF != 0, NT) : 0));
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_hop<P, false, true, MF, false, BLK>),
@@ -1251,6 +1344,7 @@ int hop_occupancy(int prec, bool mfma, bool blk, int NS, int Ls) {
     if (prec == P16 && mfma) return blk ? hop_wg_per_cu<P16, 3, true>(NS, Ls) : hop_wg_per_cu<P16, 3, false>(NS, Ls);
     if (prec == PB16 && mfma) return blk ? hop_wg_per_cu<PB16, 3, true>(NS, Ls) : hop_wg_per_cu<PB16, 3, false>(NS, Ls);
     if (prec == P32) return blk ? hop_wg_per_cu<P32, 0, true>(NS, Ls) : hop_wg_per_cu<P32, 0, false>(NS, Ls);
+    if (prec == P64) return blk ? hop_wg_per_cu<P64, 0, true>(NS, Ls) : hop_wg_per_cu<P64, 0, false>(NS, Ls);
     return 0;
 }
 

@@ -339,8 +339,9 @@ hipError_t launch_hb_accum(void* phi, const void* ce, const void* co, const doub
 // site in slot j of block b (sites[8 b + j]) for output parity p, the 8
 // direction records of a block's 8 slots contiguous.  16-bit compact links
 // (wide = 0): source [p][d][Vh][9] words, 36 B records; FP32 links (wide =
-// 1): source [p][d][9][Vh] complex, 72 B records.  Padding slots get zeros.
-// One work-item per record.
+// 1): source [p][d][9][Vh] complex, 72 B records; FP64 links (wide = 2):
+// the same source layout with 144 B records, in the phase order of the FP64
+// block hop.  Padding slots get zeros.  One work-item per record.
 __global__ void k_links_blocked(const void* __restrict__ src, void* __restrict__ dst,
                                 const int* __restrict__ sites, int Vh, int nblk, int wide) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,7 +349,20 @@ __global__ void k_links_blocked(const void* __restrict__ src, void* __restrict__
     const int j = t & 7, d = (t >> 3) & 7, pb = t >> 6;
     const int p = pb / nblk, b = pb - p * nblk;
     const int site = sites[8 * b + j];
-    if (wide) {
+    if (wide == 2) {
+        // FP64: records in phase order, (ph, k, j) with the direction of phase
+        // ph, slot k for slot j's offsets (the FP64 block hop stages one
+        // phase's 16 records at a time): phases 0, 1 the inside directions of
+        // mu = 2 (ph mod 2) + k, phases 2, 3 the outside ones
+        const int ph = (t >> 4) & 3, k2 = (t >> 3) & 1;
+        const int off = (j << 1) | ((__popc(j) + p) & 1);
+        const int mu = 2 * (ph & 1) + k2;
+        const int din = mu + 4 * ((off >> mu) & 1);
+        const int dd = ph < 2 ? din : din ^ 4;
+        const double2* in = reinterpret_cast<const double2*>(src) + ((size_t)p * 8 + dd) * 9 * Vh;
+        double2* out = reinterpret_cast<double2*>(dst) + (size_t)t * 9;
+        for (int k = 0; k < 9; ++k) out[k] = site < Vh ? in[(size_t)k * Vh + site] : make_double2(0.0, 0.0);
+    } else if (wide) {
         const float2* in = reinterpret_cast<const float2*>(src) + ((size_t)p * 8 + d) * 9 * Vh;
         float2* out = reinterpret_cast<float2*>(dst) + (size_t)t * 9;
         for (int k = 0; k < 9; ++k) out[k] = site < Vh ? in[(size_t)k * Vh + site] : make_float2(0.f, 0.f);

@@ -67,7 +67,7 @@ __device__ __forceinline__ void force_from_B(const cplx (&B)[9], const double2* 
 }
 
 // Work-item (site, s) of parity p, workgroups of NS whole sites
-// x Ls slices in the traversal of the FP64 hop (site table, XCD ranges).
+// x Ls slices in the per-site FP64 traversal (site table, XCD ranges).
 // chi_L, chi_R in the FP64 device layout (block c of 5D site n at
 // base[c N + n], n = cb Ls + s).  For each system and direction mu every
 // work-item forms its slice's term of
