@@ -124,3 +124,28 @@ def test_traversal_layouts(tile, blocks, monkeypatch):
                 out = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, dagger=True, eo=True, prec=prec).cpu().numpy()
                 assert rel(out, ref_s) < PREC_TOL[prec]
                 assert region_rel(out, ref_s) < PREC_TOL[prec]
+
+
+@pytest.mark.parametrize("L,Ls", [((4, 4, 4, 4), 8), ((2, 2, 4, 4), 24), ((4, 4, 2, 2), 16)])
+def test_gauge_update_reaches_every_link_copy(L, Ls):
+    """After eofa_ctx_update_gauge every precision's derived links (the
+    FP32 copy, the compact 16-bit links of the matrix-core paths and the
+    block-major copies of the block-sharing hops, each built on first use)
+    follow the new field: D_DWF and Mhat equal the oracle's on the second
+    field, in every precision."""
+    from paper_1611_00298_amd import Context
+    U1 = din.random_gauge(L, 0.4, 41)
+    U2 = din.random_gauge(L, 0.4, 42)
+    psi = din.gaussian_5d(L, Ls, 43)
+    lat = oracle.Lattice(L, Ls, M5=1.8, alpha=2.0)
+    with Context(L, Ls, to_dev(U1), M5=1.8, alpha=2.0) as ctx:
+        for prec in ("fp64", "fp32", "fp16", "bf16"):   # build every derived copy on U1
+            ctx.dwf_apply(to_dev(psi), 0.04, 1.0, eo=True, prec=prec)
+        ctx.update_gauge(to_dev(U2))
+        ref = oracle.ddwf(lat, U2, 0.04, 1.0, psi)
+        ref_s = oracle.schur(lat, U2, 0.04, 1.0, psi, dagger=True)
+        for prec in ("fp64", "fp32", "fp16", "bf16"):
+            out = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, prec=prec).cpu().numpy()
+            assert rel(out, ref) < PREC_TOL[prec]
+            out = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, dagger=True, eo=True, prec=prec).cpu().numpy()
+            assert rel(out, ref_s) < PREC_TOL[prec]
