@@ -186,37 +186,93 @@ __device__ __forceinline__ void stage_links(const HopArgs& a, int lb, unsigned c
 // the links (a.lnkb: the 64 records of a block contiguous, record (d, j) of
 // 36 B compact 16-bit or 72 B FP32 links), so that a workgroup's link loads
 // cover a few whole cache lines instead of one partial line per record.
-// Consecutive work-items read consecutive words.
+// Consecutive work-items read consecutive words.  The staging has two parts:
+// links_fetch issues the loads of a work-item's first LinkPre::K elements
+// into registers, all at once and before the neighbour gathers, and
+// links_put writes them to LDS, so that its writes wait for the links alone
+// while the gathers stay in flight; elements beyond the first K (Ls < 16)
+// are staged by links_put in further batches of K.
+template <int P, int MF> struct LinkPre {
+    static constexpr int K = 4;
+    static constexpr int W = MF ? 3 : 2;   // 32-bit words per element
+    static constexpr int E = MF ? 64 : 72; // elements per slot
+    uint32_t w[K][W];
+};
+
 template <int P, int MF>
-__device__ __forceinline__ void stage_links_blk(const HopArgs& a, int lb, unsigned char* lds) {
+__device__ __forceinline__ void links_load(const HopArgs& a, int lb, int e0, LinkPre<P, MF>& pre) {
+    using LP = LinkPre<P, MF>;
+    const int NS = a.NS, NT = blockDim.x, last = NS * LP::E - 1;
+    // first word of the workgroup's blocks: 64 records of 9 words (MF) or 9 word pairs
+    const uint32_t* g = reinterpret_cast<const uint32_t*>(a.lnkb) + (size_t)lb * (NS >> 3) * 64 * 9 * (MF ? 1 : 2);
+#pragma unroll
+    for (int u = 0; u < LP::K; ++u) {
+        // out-of-range elements (beyond the workgroup's records, or the zero
+        // rows 6 and 7 of a matrix-core record) read a valid word and are
+        // discarded by links_write
+        const int e = min(e0 + u * NT, last);
+        if constexpr (MF != 0) {
+            const int r = e & 7, q = e >> 3;
+            const uint32_t* w = g + (size_t)q * 9 + 3 * (min(r, 5) >> 1);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pre.w[u][k] = __builtin_nontemporal_load(w + k);   // read once per launch
+        } else {
+            const uint2 v = reinterpret_cast<const uint2*>(g)[e];
+            pre.w[u][0] = v.x;
+            pre.w[u][1] = v.y;
+        }
+    }
+}
+
+template <int P, int MF>
+__device__ __forceinline__ void links_write(const HopArgs& a, int e0, const LinkPre<P, MF>& pre,
+                                            unsigned char* lds) {
+    using LP = LinkPre<P, MF>;
     constexpr int LB = LinkLds<P, MF>::LB;
-    const int NS = a.NS, NT = blockDim.x, tid = threadIdx.x;
-    const size_t blk0 = (size_t)lb * (NS >> 3);   // first block of the workgroup
-    if constexpr (MF != 0) {
-        // as stage_links: row r of the real 6x6 form from 3 words of the record
-        const uint32_t* g = reinterpret_cast<const uint32_t*>(a.lnkb) + blk0 * 64 * 9;
-        for (int e = tid; e < NS * 64; e += NT) {
-            const int r = e & 7, q = e >> 3;   // q = (block, d, slot) record index in the workgroup
+    const int NS = a.NS, NT = blockDim.x, n = NS * LP::E;
+    // elements beyond the workgroup's records write to a dummy word after the
+    // records (the unused index area of stage_bytes): every write is issued
+    // unconditionally, which keeps the loads of links_fetch where they are
+    unsigned char* dummy = lds + (size_t)NS * 8 * LB;
+#pragma unroll
+    for (int u = 0; u < LP::K; ++u) {
+        const int e = e0 + u * NT;
+        const bool ok = e < n;
+        const int ec = ok ? e : 0;
+        if constexpr (MF != 0) {
+            // row r of the real 6x6 form from 3 words of the record (as stage_links)
+            const int r = ec & 7, q = ec >> 3;   // q = (block, d, slot) record index in the workgroup
             const int jj = q & 7, d = (q >> 3) & 7, j = ((q >> 6) << 3) + jj;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (r < 6) {
-                const uint32_t* w = g + (size_t)q * 9 + 3 * (r >> 1);
-                const uint32_t w0 = __builtin_nontemporal_load(w), w1 = __builtin_nontemporal_load(w + 1),
-                               w2 = __builtin_nontemporal_load(w + 2);   // read once per launch
-                if (r & 1) v = make_uint4(__builtin_amdgcn_alignbit(w0, w0, 16), __builtin_amdgcn_alignbit(w1, w1, 16),
-                                          __builtin_amdgcn_alignbit(w2, w2, 16), 0u);
-                else v = make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
-            }
-            *reinterpret_cast<uint4*>(lds + (j * 8 + d) * LB + 16 * r) = v;
-        }
-    } else {
-        static_assert(P == P32, "the vector block path stages FP32 links (FP64: hop_blk_f64)");
-        const float2* g = reinterpret_cast<const float2*>(a.lnkb) + blk0 * 64 * 9;
-        for (int e = tid; e < NS * 72; e += NT) {
-            const int q = e / 9, k = e - 9 * q;
+            const uint32_t w0 = pre.w[u][0], w1 = pre.w[u][1], w2 = pre.w[u][2];
+            uint4 v = (r & 1) ? make_uint4(__builtin_amdgcn_alignbit(w0, w0, 16), __builtin_amdgcn_alignbit(w1, w1, 16),
+                                           __builtin_amdgcn_alignbit(w2, w2, 16), 0u)
+                              : make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
+            if (r >= 6) v = make_uint4(0, 0, 0, 0);
+            *reinterpret_cast<uint4*>(ok ? lds + (j * 8 + d) * LB + 16 * r : dummy) = v;
+        } else {
+            static_assert(P == P32, "the vector block path stages FP32 links (FP64: hop_blk_f64)");
+            const int q = ec / 9, k = ec - 9 * q;
             const int jj = q & 7, d = (q >> 3) & 7, j = ((q >> 6) << 3) + jj;
-            *reinterpret_cast<float2*>(lds + (j * 8 + d) * LB + 8 * k) = g[e];
+            *reinterpret_cast<uint2*>(ok ? lds + (j * 8 + d) * LB + 8 * k : dummy) = make_uint2(pre.w[u][0], pre.w[u][1]);
         }
+    }
+}
+
+template <int P, int MF>
+__device__ __forceinline__ void links_fetch(const HopArgs& a, int lb, LinkPre<P, MF>& pre) {
+    links_load<P, MF>(a, lb, threadIdx.x, pre);
+}
+
+template <int P, int MF>
+__device__ __forceinline__ void links_put(const HopArgs& a, int lb, const LinkPre<P, MF>& pre, unsigned char* lds) {
+    using LP = LinkPre<P, MF>;
+    const int NT = blockDim.x;
+    links_write<P, MF>(a, threadIdx.x, pre, lds);
+#pragma unroll 1
+    for (int e0 = threadIdx.x + LP::K * NT; e0 < a.NS * LP::E; e0 += LP::K * NT) {
+        LinkPre<P, MF> more;
+        links_load<P, MF>(a, lb, e0, more);
+        links_write<P, MF>(a, e0, more, lds);
     }
 }
 
@@ -382,11 +438,15 @@ __device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned c
     int nbo[4];
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) nbo[mu] = nb[8 * (mu + 1)];
+    LinkPre<P, 0> pre;
+    links_fetch<P, 0>(a, lb, pre);
+    __builtin_amdgcn_sched_barrier(0);
     Stage<P> sx, o[2];
     load_stage<P>(a, s, nb[0], sx);
     load_stage<P>(a, s, nbo[0], o[0]);
     load_stage<P>(a, s, nbo[1], o[1]);
-    stage_links_blk<P, 0>(a, lb, lds);
+    __builtin_amdgcn_sched_barrier(0);
+    links_put<P, 0>(a, lb, pre, lds);
     put(sx);
     __syncthreads();
     compute_stage_sg<P, 0>(sx, lr + din(0) * LB, sgn(din(0)), acc);
@@ -453,20 +513,29 @@ __device__ __forceinline__ void hop_blk_f64(const HopArgs& a, int lb, unsigned c
             st.psi[2 * c + 1] = w.y;
         }
     };
+    // each phase's link element is loaded one phase ahead, so that the
+    // stores between the barriers do not wait for memory
+    double2 lnext = fetch(0);
     auto next_phase = [&](int ph) {   // every work-item; the previous phase's records are read
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
-        store(fetch(ph));
+        store(lnext);
+        if (ph < 3) lnext = fetch(ph + 1);
         __syncthreads();
         __builtin_amdgcn_sched_barrier(0);
     };
     const unsigned char* l0 = lk + sl * 2 * LB;
     const unsigned char* l1 = l0 + LB;
+    // the outside neighbours' indices, loaded before the first barrier
+    int nbo[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) nbo[mu] = nb[8 * (mu + 1)];
     Stage<P> st;
     // phase 0: inside x (this work-item's load, shared) and inside y
     load_stage<P>(a, s, nb[0], st);
+    store(lnext);
+    lnext = fetch(1);
     share(st);
-    store(fetch(0));
     __syncthreads();
     compute_stage_sg<P, 0>(st, l0, sgn(dir(0, 0)), acc);
     __builtin_amdgcn_sched_barrier(0);
@@ -479,16 +548,16 @@ __device__ __forceinline__ void hop_blk_f64(const HopArgs& a, int lb, unsigned c
     get((sl ^ 4) * a.Ls + s, st);
     compute_stage_sg<P, 3>(st, l1, sgn(dir(1, 1)), acc);
     next_phase(2);   // outside x and y
-    load_stage<P>(a, s, nb[8], st);
+    load_stage<P>(a, s, nbo[0], st);
     compute_stage_sg<P, 0>(st, l0, sgn(dir(2, 0)), acc);
     __builtin_amdgcn_sched_barrier(0);
-    load_stage<P>(a, s, nb[16], st);
+    load_stage<P>(a, s, nbo[1], st);
     compute_stage_sg<P, 1>(st, l1, sgn(dir(2, 1)), acc);
     next_phase(3);   // outside z and t
-    load_stage<P>(a, s, nb[24], st);
+    load_stage<P>(a, s, nbo[2], st);
     compute_stage_sg<P, 2>(st, l0, sgn(dir(3, 0)), acc);
     __builtin_amdgcn_sched_barrier(0);
-    load_stage<P>(a, s, nb[32], st);
+    load_stage<P>(a, s, nbo[3], st);
     compute_stage_sg<P, 3>(st, l1, sgn(dir(3, 1)), acc);
 }
 
@@ -751,11 +820,15 @@ __device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned 
     int nbo[4];
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) nbo[mu] = nb[8 * (mu + 1)];
+    LinkPre<P, 1> pre;
+    links_fetch<P, 1>(a, lb, pre);
+    __builtin_amdgcn_sched_barrier(0);
     MStage sx, o[2];
     load_mstage<P>(a, s, nbx, sx);
     load_mstage<P>(a, s, nbo[0], o[0]);
     load_mstage<P>(a, s, nbo[1], o[1]);
-    stage_links_blk<P, 1>(a, lb, lds);
+    __builtin_amdgcn_sched_barrier(0);
+    links_put<P, 1>(a, lb, pre, lds);
     uint4* sh = reinterpret_cast<uint4*>(lds + stage_bytes(LB, a.NS));
     float* shn = reinterpret_cast<float*>(sh + 3 * NT);
 #pragma unroll
