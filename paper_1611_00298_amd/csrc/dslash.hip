@@ -230,15 +230,12 @@ __device__ __forceinline__ void links_write(const HopArgs& a, int e0, const Link
     using LP = LinkPre<P, MF>;
     constexpr int LB = LinkLds<P, MF>::LB;
     const int NS = a.NS, NT = blockDim.x, n = NS * LP::E;
-    // elements beyond the workgroup's records write to a dummy word after the
-    // records (the unused index area of stage_bytes): every write is issued
+    // work-items beyond the workgroup's records repeat the last element (the
+    // value links_load fetched for it), so that every write is issued
     // unconditionally, which keeps the loads of links_fetch where they are
-    unsigned char* dummy = lds + (size_t)NS * 8 * LB;
 #pragma unroll
     for (int u = 0; u < LP::K; ++u) {
-        const int e = e0 + u * NT;
-        const bool ok = e < n;
-        const int ec = ok ? e : 0;
+        const int ec = min(e0 + u * NT, n - 1);
         if constexpr (MF != 0) {
             // row r of the real 6x6 form from 3 words of the record (as stage_links)
             const int r = ec & 7, q = ec >> 3;   // q = (block, d, slot) record index in the workgroup
@@ -248,12 +245,12 @@ __device__ __forceinline__ void links_write(const HopArgs& a, int e0, const Link
                                            __builtin_amdgcn_alignbit(w2, w2, 16), 0u)
                               : make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
             if (r >= 6) v = make_uint4(0, 0, 0, 0);
-            *reinterpret_cast<uint4*>(ok ? lds + (j * 8 + d) * LB + 16 * r : dummy) = v;
+            *reinterpret_cast<uint4*>(lds + (j * 8 + d) * LB + 16 * r) = v;
         } else {
             static_assert(P == P32, "the vector block path stages FP32 links (FP64: hop_blk_f64)");
             const int q = ec / 9, k = ec - 9 * q;
             const int jj = q & 7, d = (q >> 3) & 7, j = ((q >> 6) << 3) + jj;
-            *reinterpret_cast<uint2*>(ok ? lds + (j * 8 + d) * LB + 8 * k : dummy) = make_uint2(pre.w[u][0], pre.w[u][1]);
+            *reinterpret_cast<uint2*>(lds + (j * 8 + d) * LB + 8 * k) = make_uint2(pre.w[u][0], pre.w[u][1]);
         }
     }
 }
@@ -283,9 +280,19 @@ template <int P> struct Stage {
     float nrm;
 };
 
+// 5D index nb Ls + s of a neighbour's slice as a separate 32-bit multiply and
+// add.  Fused into one 64-bit multiply-add, the unused high word of the
+// addend may be given a register whose load is still in flight, and the
+// gather then waits for every outstanding load.
+__device__ __forceinline__ uint32_t slice5(int nb, int Ls, int s) {
+    uint32_t m = (uint32_t)nb * (uint32_t)Ls;
+    asm volatile("" : "+v"(m));
+    return m + (uint32_t)s;
+}
+
 template <int P>
-__device__ __forceinline__ void load_stage(const HopArgs& a, int s, int nb, Stage<P>& st) {
-    const size_t n = (size_t)nb * a.Ls + s;
+__device__ __forceinline__ void load_stage(const HopArgs& a, int s, int nb, Stage<P>& st, bool split = false) {
+    const size_t n = split ? slice5(nb, a.Ls, s) : (size_t)nb * a.Ls + s;
     if constexpr (P == P16 || P == PB16) st.nrm = ld_spinor_raw<P>(a.in, a.in_nrm, a.N, n, st.psi);
     else ld_spinor<P>(a.in, a.in_nrm, a.N, n, st.psi);
 }
@@ -442,19 +449,19 @@ __device__ __forceinline__ void hop_blk_vec(const HopArgs& a, int lb, unsigned c
     links_fetch<P, 0>(a, lb, pre);
     __builtin_amdgcn_sched_barrier(0);
     Stage<P> sx, o[2];
-    load_stage<P>(a, s, nb[0], sx);
-    load_stage<P>(a, s, nbo[0], o[0]);
-    load_stage<P>(a, s, nbo[1], o[1]);
+    load_stage<P>(a, s, nb[0], sx, true);
+    load_stage<P>(a, s, nbo[0], o[0], true);
+    load_stage<P>(a, s, nbo[1], o[1], true);
     __builtin_amdgcn_sched_barrier(0);
     links_put<P, 0>(a, lb, pre, lds);
     put(sx);
     __syncthreads();
     compute_stage_sg<P, 0>(sx, lr + din(0) * LB, sgn(din(0)), acc);
     outside(I0{}, o[0]);
-    load_stage<P>(a, s, nbo[2], o[0]);
+    load_stage<P>(a, s, nbo[2], o[0], true);
     inside(I1{}, sx);
     outside(I1{}, o[1]);
-    load_stage<P>(a, s, nbo[3], o[1]);
+    load_stage<P>(a, s, nbo[3], o[1], true);
     inside(I2{}, sx);
     outside(I2{}, o[0]);
     inside(I3{}, sx);
@@ -641,8 +648,8 @@ struct MStage {
 };
 
 template <int P>
-__device__ __forceinline__ void load_mstage(const HopArgs& a, int s, int nb, MStage& st) {
-    const uint32_t n = (uint32_t)nb * a.Ls + s;
+__device__ __forceinline__ void load_mstage(const HopArgs& a, int s, int nb, MStage& st, bool split = false) {
+    const uint32_t n = split ? slice5(nb, a.Ls, s) : (uint32_t)nb * a.Ls + s;
     const uint32_t off = n * 16u;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -824,9 +831,9 @@ __device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned 
     links_fetch<P, 1>(a, lb, pre);
     __builtin_amdgcn_sched_barrier(0);
     MStage sx, o[2];
-    load_mstage<P>(a, s, nbx, sx);
-    load_mstage<P>(a, s, nbo[0], o[0]);
-    load_mstage<P>(a, s, nbo[1], o[1]);
+    load_mstage<P>(a, s, nbx, sx, true);
+    load_mstage<P>(a, s, nbo[0], o[0], true);
+    load_mstage<P>(a, s, nbo[1], o[1], true);
     __builtin_amdgcn_sched_barrier(0);
     links_put<P, 1>(a, lb, pre, lds);
     uint4* sh = reinterpret_cast<uint4*>(lds + stage_bytes(LB, a.NS));
@@ -860,10 +867,10 @@ __device__ __forceinline__ void hop_blk_mfma(const HopArgs& a, int lb, unsigned 
     using I3 = std::integral_constant<int, 3>;
     compute_mstage_sg<P, 0>(sx, lr + din(0) * LB, lane4, sgn(din(0)), acc);
     outside(I0{}, o[0]);
-    load_mstage<P>(a, s, nbo[2], o[0]);
+    load_mstage<P>(a, s, nbo[2], o[0], true);
     inside(I1{});
     outside(I1{}, o[1]);
-    load_mstage<P>(a, s, nbo[3], o[1]);
+    load_mstage<P>(a, s, nbo[3], o[1], true);
     inside(I2{});
     outside(I2{}, o[0]);
     inside(I3{});
