@@ -99,6 +99,10 @@ __global__ void __launch_bounds__(256, 3) k_force_dev(const double2* __restrict_
     const double2* othR = p ? chiRe : chiRo;
     double* sums = red + (size_t)NT * 19;
     const size_t na = (size_t)cb * Ls + s;
+    // the forward neighbours' indices, loaded once and before any gather
+    int nbf[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) nbf[mu] = active ? nbr[((size_t)p * 8 + mu) * g.Vh + cb] : 0;
     // chi_L then chi_R: the work-item's own spinor is loaded once per system
     // and kept in registers over the four directions
 #pragma unroll 1
@@ -112,8 +116,7 @@ __global__ void __launch_bounds__(256, 3) k_force_dev(const double2* __restrict_
             cplx acc[9];
             for (int q = 0; q < 9; ++q) acc[q] = {0.0, 0.0};
             if (active) {
-                const int nb = nbr[((size_t)p * 8 + mu) * g.Vh + cb];
-                const size_t nn = (size_t)nb * Ls + (Ls - 1 - s);
+                const size_t nn = (size_t)nbf[mu] * Ls + (Ls - 1 - s);
                 cplx h[2][3], gg[2][3];
                 for (int cc = 0; cc < 3; ++cc) {
                     const double2 b0 = b[cc * N + nn], b1 = b[(3 + cc) * N + nn];
