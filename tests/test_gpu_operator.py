@@ -96,17 +96,19 @@ def test_force_parity_shapes(setup):
     assert np.abs(G.cpu().numpy() - Gr).max() <= 1e-12 * np.abs(Gr).max()
 
 
-@pytest.mark.parametrize("blocks", ["1", "0"])
+@pytest.mark.parametrize("blocks", ["1", "0", "2"])
 @pytest.mark.parametrize("tile", ["p2,2,2,2,2,1,t", "p1,2,4,4,2,1,t", "p2,4,1,2,1,2,t", "z,2,1,1,t", "p2,2,1,2,2,1,t",
                                   "q2,1,2,2,1,2,1,1,t", "q1,1,2,4,2,2,2,1,z", "none"])
 def test_traversal_layouts(tile, blocks, monkeypatch):
     """The hop's site traversal (the XCD regions and tiles of EOFA_TILE, a
-    tuning override; with EOFA_BLOCKS=1, the default, the matrix-core paths
-    walk whole 2x2x2x2 blocks and share their inside neighbours through LDS)
-    only reorders the work: D_DWF and Mhat in FP64, FP16 and BF16 equal the
-    oracle's under every layout, including partitions into fewer than 8
-    regions (which fall back to the natural order), and for workgroups of 1
-    (Ls = 24) and 3 (Ls = 8) blocks."""
+    tuning override; with EOFA_BLOCKS=1, the default, the hops walk whole
+    2x2x2x2 blocks and share their inside neighbours through LDS where that
+    costs no occupancy, 2 forces the block form, 0 turns it off) only
+    reorders the work: D_DWF and Mhat in every precision equal the oracle's
+    under every layout, including partitions into fewer than 8 regions
+    (which fall back to the natural order), and for workgroups of 1
+    (Ls = 24) and 3 (Ls = 8) blocks; at Ls = 8 the forced block form stages
+    its links in several batches per work-item."""
     from paper_1611_00298_amd import Context
     monkeypatch.setenv("EOFA_TILE", tile)
     monkeypatch.setenv("EOFA_BLOCKS", blocks)
@@ -117,7 +119,7 @@ def test_traversal_layouts(tile, blocks, monkeypatch):
         ref = oracle.ddwf(lat, U, 0.04, 1.0, psi)
         ref_s = oracle.schur(lat, U, 0.04, 1.0, psi, dagger=True)
         with Context(L, Ls, to_dev(U), M5=1.8, alpha=2.0) as ctx:
-            for prec in ("fp64", "fp16", "bf16"):
+            for prec in ("fp64", "fp32", "fp16", "bf16"):
                 out = ctx.dwf_apply(to_dev(psi), 0.04, 1.0, prec=prec).cpu().numpy()
                 assert rel(out, ref) < PREC_TOL[prec]
                 assert region_rel(out, ref) < PREC_TOL[prec]
