@@ -132,38 +132,20 @@ __device__ __forceinline__ int slot_site(const HopArgs& a, int lb, int j) {
     return site < a.Vh ? site : 0;   // padding slots read site 0 and discard it
 }
 
-template <int P, int MF>
+template <int P>
 __device__ __forceinline__ void stage_links(const HopArgs& a, int lb, unsigned char* lds) {
-    constexpr int LB = LinkLds<P, MF>::LB;
+    constexpr int LB = LinkLds<P, 0>::LB;
     const int NS = a.NS, NT = blockDim.x, tid = threadIdx.x;
-    if constexpr (P == P64) {   // FP64 also stages the neighbour indices, after the links
+    // FP32 (vector paths) or FP64 links; FP64 also stages the neighbour
+    // indices, placed after the links
+    if constexpr (P == P64) {
         int* nbl = reinterpret_cast<int*>(lds + (size_t)NS * 8 * LB);
         for (int e = tid; e < NS * 8; e += NT) {
             const int j = e % NS, d = e / NS;
             nbl[j * 8 + d] = a.nbr[(size_t)d * a.Vh + slot_site(a, lb, j)];
         }
     }
-    if constexpr (MF != 0) {
-        // expand the compact FP16 link (9 (re, im) half pairs) into the rows
-        // of its real 6x6 form: row 2a   = (Ur_ab, -Ui_ab) for b = 0..2, 0,
-        //                       row 2a+1 = (Ui_ab,  Ur_ab) for b = 0..2, 0;
-        // rows 6 and 7 are zero.  Work-item e builds row e & 7 of record e >> 3.
-        const uint32_t* g = reinterpret_cast<const uint32_t*>(a.frag);
-        for (int e = tid; e < NS * 64; e += NT) {
-            const int r = e & 7, jd = e >> 3;
-            const int j = jd % NS, d = jd / NS;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (r < 6) {
-                const uint32_t* w = g + ((size_t)d * a.Vh + slot_site(a, lb, j)) * 9 + 3 * (r >> 1);
-                const uint32_t w0 = __builtin_nontemporal_load(w), w1 = __builtin_nontemporal_load(w + 1),
-                               w2 = __builtin_nontemporal_load(w + 2);   // read once per launch
-                if (r & 1) v = make_uint4(__builtin_amdgcn_alignbit(w0, w0, 16), __builtin_amdgcn_alignbit(w1, w1, 16),
-                                          __builtin_amdgcn_alignbit(w2, w2, 16), 0u);
-                else v = make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
-            }
-            *reinterpret_cast<uint4*>(lds + (j * 8 + d) * LB + 16 * r) = v;
-        }
-    } else if constexpr (P == P64) {
+    if constexpr (P == P64) {
         const size_t bb = (size_t)a.Vh * 16;
         for (int e = tid; e < NS * 72; e += NT) {
             const int j = e % NS, dk = e / NS;
@@ -237,7 +219,9 @@ __device__ __forceinline__ void links_write(const HopArgs& a, int e0, const Link
     for (int u = 0; u < LP::K; ++u) {
         const int ec = min(e0 + u * NT, n - 1);
         if constexpr (MF != 0) {
-            // row r of the real 6x6 form from 3 words of the record (as stage_links)
+            // row r of the compact link's real 6x6 form, from 3 words of the
+            // record (9 (re, im) half pairs): row 2a = (Ur_ab, -Ui_ab) for
+            // b = 0..2, then 0; row 2a+1 = (Ui_ab, Ur_ab), then 0; rows 6, 7 zero
             const int r = ec & 7, q = ec >> 3;   // q = (block, d, slot) record index in the workgroup
             const int jj = q & 7, d = (q >> 3) & 7, j = ((q >> 6) << 3) + jj;
             const uint32_t w0 = pre.w[u][0], w1 = pre.w[u][1], w2 = pre.w[u][2];
@@ -270,6 +254,52 @@ __device__ __forceinline__ void links_put(const HopArgs& a, int lb, const LinkPr
         LinkPre<P, MF> more;
         links_load<P, MF>(a, lb, e0, more);
         links_write<P, MF>(a, e0, more, lds);
+    }
+}
+
+// The same two-part staging for the per-site matrix-core path, by the
+// slot's own work-items, whose site is known (no table lookup that would
+// have to wait behind the gathers): work-item (sl, s) builds rows
+// q = s, s + Ls, ... of its slot's 8 records (q = 8 d + r); rows past the
+// last repeat it (a zero row).
+template <int P>
+__device__ __forceinline__ void links_load_site(const HopArgs& a, int site, int q0, LinkPre<P, 1>& pre) {
+    const uint32_t* g = reinterpret_cast<const uint32_t*>(a.frag);
+#pragma unroll
+    for (int u = 0; u < LinkPre<P, 1>::K; ++u) {
+        const int q = min(q0 + u * a.Ls, 63), d = q >> 3, r = q & 7;
+        const uint32_t* w = g + ((size_t)d * a.Vh + site) * 9 + 3 * (min(r, 5) >> 1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pre.w[u][k] = __builtin_nontemporal_load(w + k);   // read once per launch
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void links_write_site(const HopArgs& a, int sl, int q0, const LinkPre<P, 1>& pre,
+                                                 unsigned char* lds) {
+    constexpr int LB = LinkLds<P, 1>::LB;
+#pragma unroll
+    for (int u = 0; u < LinkPre<P, 1>::K; ++u) {
+        const int q = min(q0 + u * a.Ls, 63), d = q >> 3, r = q & 7;   // row r as in links_write
+        const uint32_t w0 = pre.w[u][0], w1 = pre.w[u][1], w2 = pre.w[u][2];
+        uint4 v = (r & 1) ? make_uint4(__builtin_amdgcn_alignbit(w0, w0, 16), __builtin_amdgcn_alignbit(w1, w1, 16),
+                                       __builtin_amdgcn_alignbit(w2, w2, 16), 0u)
+                          : make_uint4(w0 ^ 0x80000000u, w1 ^ 0x80000000u, w2 ^ 0x80000000u, 0u);
+        if (r >= 6) v = make_uint4(0, 0, 0, 0);
+        *reinterpret_cast<uint4*>(lds + (sl * 8 + d) * LB + 16 * r) = v;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void links_put_site(const HopArgs& a, int site, int sl, int s, const LinkPre<P, 1>& pre,
+                                               unsigned char* lds) {
+    constexpr int K = LinkPre<P, 1>::K;
+    links_write_site<P>(a, sl, s, pre, lds);
+#pragma unroll 1
+    for (int q0 = s + K * a.Ls; q0 < 64; q0 += K * a.Ls) {
+        LinkPre<P, 1> more;
+        links_load_site<P>(a, site, q0, more);
+        links_write_site<P>(a, sl, q0, more, lds);
     }
 }
 
@@ -366,7 +396,7 @@ __device__ __forceinline__ void hop_all(const HopArgs& a, int lb, unsigned char*
     Stage<P> st[DEPTH];
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) load_stage<P>(a, s, nb[d], st[d]);
-    stage_links<P, 0>(a, lb, lds);
+    stage_links<P>(a, lb, lds);
     __syncthreads();
     const unsigned char* lr = lds + sl * 8 * LB;
 #pragma unroll
@@ -783,10 +813,16 @@ __device__ __forceinline__ void hop_all_mfma(const HopArgs& a, int lb, unsigned 
     int nb[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) nb[d] = a.nbr[(size_t)d * a.Vh + site];
+    // the links first, written to LDS after the gathers are issued (as in
+    // hop_blk_mfma)
+    LinkPre<P, 1> pre;
+    links_load_site<P>(a, site, s, pre);
+    __builtin_amdgcn_sched_barrier(0);
     MStage st[DEPTH];
 #pragma unroll
-    for (int d = 0; d < DEPTH; ++d) load_mstage<P>(a, s, nb[d], st[d]);
-    stage_links<P, 1>(a, lb, lds);
+    for (int d = 0; d < DEPTH; ++d) load_mstage<P>(a, s, nb[d], st[d], true);
+    __builtin_amdgcn_sched_barrier(0);
+    links_put_site<P>(a, site, sl, s, pre, lds);
     __syncthreads();
     const unsigned char* lr = lds + sl * 8 * LB;
 #pragma unroll
@@ -1120,7 +1156,7 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) 
         // every work-item takes part (staging barrier; the MFMA needs the
         // whole wave); padding work-items read site 0 and discard it
         if constexpr (P == P64 && !BLK) {
-            stage_links<P, 0>(a, lb, smem_raw);
+            stage_links<P>(a, lb, smem_raw);
             __syncthreads();
         }
         if constexpr (MF && BLK) hop_blk_mfma<P, DAG>(a, lb, smem_raw, sl, s, tid & 3, v);
