@@ -126,40 +126,32 @@ __host__ __device__ constexpr size_t stage_bytes(int lb_bytes, int NS) {
     return (size_t)NS * 8 * lb_bytes + (size_t)NS * 8 * sizeof(int);
 }
 
-__device__ __forceinline__ int slot_site(const HopArgs& a, int lb, int j) {
-    const int slot = lb * a.NS + j;
-    const int site = a.sites ? a.sites[slot] : slot;
-    return site < a.Vh ? site : 0;   // padding slots read site 0 and discard it
-}
-
+// Per-site paths (FP32 links for the vector paths, FP64 links for FP64):
+// each slot's work-items stage their own slot's 72 link elements (q = 9 d + k)
+// in batches of 4 per work-item, work-item (sl, s) taking q = s, s + Ls, ...;
+// the site is the work-item's own, so no load waits on a table lookup.  FP64
+// also stages the slot's 8 neighbour indices, placed after the links.
+// Elements past the last repeat it (the same value to the same place).
 template <int P>
-__device__ __forceinline__ void stage_links(const HopArgs& a, int lb, unsigned char* lds) {
+__device__ __forceinline__ void stage_links(const HopArgs& a, int site, int sl, int s, unsigned char* lds) {
     constexpr int LB = LinkLds<P, 0>::LB;
-    const int NS = a.NS, NT = blockDim.x, tid = threadIdx.x;
-    // FP32 (vector paths) or FP64 links; FP64 also stages the neighbour
-    // indices, placed after the links
+    using T = typename std::conditional<P == P64, double2, float2>::type;
+    const int Ls = a.Ls;
     if constexpr (P == P64) {
-        int* nbl = reinterpret_cast<int*>(lds + (size_t)NS * 8 * LB);
-        for (int e = tid; e < NS * 8; e += NT) {
-            const int j = e % NS, d = e / NS;
-            nbl[j * 8 + d] = a.nbr[(size_t)d * a.Vh + slot_site(a, lb, j)];
-        }
+        int* nbl = reinterpret_cast<int*>(lds + (size_t)a.NS * 8 * LB) + sl * 8;
+        for (int d = s; d < 8; d += Ls) nbl[d] = a.nbr[(size_t)d * a.Vh + site];
     }
-    if constexpr (P == P64) {
-        const size_t bb = (size_t)a.Vh * 16;
-        for (int e = tid; e < NS * 72; e += NT) {
-            const int j = e % NS, dk = e / NS;
-            const int d = dk / 9, k = dk - 9 * d;
-            *reinterpret_cast<double2*>(lds + (j * 8 + d) * LB + 16 * k) =
-                at<double2>(a.gauge, (size_t)dk * bb, (uint32_t)slot_site(a, lb, j) * 16u);
-        }
-    } else {
-        const size_t bb = (size_t)a.Vh * 8;
-        for (int e = tid; e < NS * 72; e += NT) {
-            const int j = e % NS, dk = e / NS;
-            const int d = dk / 9, k = dk - 9 * d;
-            *reinterpret_cast<float2*>(lds + (j * 8 + d) * LB + 8 * k) =
-                at<float2>(a.gauge, (size_t)dk * bb, (uint32_t)slot_site(a, lb, j) * 8u);
+    const size_t bb = (size_t)a.Vh * sizeof(T);
+    const uint32_t off = (uint32_t)site * (uint32_t)sizeof(T);
+    unsigned char* rec = lds + (size_t)sl * 8 * LB;
+    for (int q0 = s; q0 < 72; q0 += 4 * Ls) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = at<T>(a.gauge, (size_t)min(q0 + u * Ls, 71) * bb, off);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = min(q0 + u * Ls, 71), d = q / 9, k = q - 9 * d;
+            *reinterpret_cast<T*>(rec + d * LB + sizeof(T) * k) = v[u];
         }
     }
 }
@@ -393,10 +385,10 @@ __device__ __forceinline__ void hop_all(const HopArgs& a, int lb, unsigned char*
     int nb[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) nb[d] = a.nbr[(size_t)d * a.Vh + site];
+    stage_links<P>(a, site, sl, s, lds);   // before the gathers: nothing to wait behind
     Stage<P> st[DEPTH];
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) load_stage<P>(a, s, nb[d], st[d]);
-    stage_links<P>(a, lb, lds);
     __syncthreads();
     const unsigned char* lr = lds + sl * 8 * LB;
 #pragma unroll
@@ -1156,7 +1148,7 @@ __global__ void __launch_bounds__(256, (MF == 3 && P == P16 && !DENSE) ? 5 : 3) 
         // every work-item takes part (staging barrier; the MFMA needs the
         // whole wave); padding work-items read site 0 and discard it
         if constexpr (P == P64 && !BLK) {
-            stage_links<P>(a, lb, smem_raw);
+            stage_links<P>(a, active ? site : 0, sl, s, smem_raw);
             __syncthreads();
         }
         if constexpr (MF && BLK) hop_blk_mfma<P, DAG>(a, lb, smem_raw, sl, s, tid & 3, v);
