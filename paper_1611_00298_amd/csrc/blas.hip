@@ -36,9 +36,18 @@ __device__ __forceinline__ void block_store_sum(double x, double* dst) {
 // dependent loads (a hop leaves one partial per workgroup: 55296 at 24^3x64).
 __global__ void __launch_bounds__(1024) k_reduce(const double* __restrict__ partial, int n,
                                                  double* out, int slot) {
+    // each work-item adds its elements in index order; 32 loads are in
+    // flight at a time (a hop's 55 296 partials take two batches)
     double t = 0;
     const int step = blockDim.x;
     int i = threadIdx.x;
+    for (; i + 31 * step < n; i += 32 * step) {
+        double v[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) v[q] = partial[i + q * step];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) t += v[q];
+    }
     for (; i + 7 * step < n; i += 8 * step) {
         double v[8];
 #pragma unroll
