@@ -167,7 +167,7 @@ struct eofa_ctx {
     int* sites[4] = {nullptr, nullptr, nullptr, nullptr};   // hop traversal (site per slot) per precision
     int blk[4] = {0, 0, 0, 0};   // the table lists whole 2x2x2x2 blocks (FP32 and matrix-core paths)
     int* nbrb[4] = {nullptr, nullptr, nullptr, nullptr};   // block-major neighbours of a block table
-    int* fsites = nullptr;   // the force kernel's traversal (the FP64 per-site table)
+    int* fsites = nullptr;   // the per-site FP64 traversal (force kernel, dense hops)
     void* lnkb[4] = {nullptr, nullptr, nullptr, nullptr};  // block-major links of a block table (P32, P16, PB16)
     void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
     void* U_nat = nullptr;
@@ -398,6 +398,10 @@ void run_hop(eofa_ctx* c, const HopCall& h) {
     if (h.dmat) {
         if ((h.prec != P64 && h.prec != P32 && h.prec != P16) || h.C.kind != 0 || h.B2.kind != 0 || h.dev_alpha)
             fail(EOFA_EDEVICE, "internal: unsupported dense hop form");
+        // the dense hops run per site: where this precision's table lists
+        // blocks they walk the per-site table instead (a block table spreads
+        // each workgroup's slots over 8 rows)
+        if (c->blk[h.prec]) a.sites = c->fsites;
         a.dmat = h.dmat;
         hipchk(launch_hop_dense(h.prec, h.dag, h.hop, a, c->nblk_hop, c->st), "dense hop kernel");
         timing_end(c, ev, h.hop ? C_HOPDENSE : C_BLAS, bytes);
@@ -1877,7 +1881,7 @@ int eofa_ctx_create(eofa_ctx_t** out, const eofa_geom_t* g, const void* U, void*
                 }
                 const std::vector<int> ord = site_order(c, default_tiling(c, p, blocks), blocks);
                 c->blk[p] = blocks;
-                if (p == P64) {   // the force kernel keeps the per-site order (faster for it)
+                if (p == P64) {   // the force kernel and the dense hops keep the per-site order (faster for them)
                     const std::vector<int> fo = blocks ? site_order(c, default_tiling(c, P64, false), false) : ord;
                     hipchk(hipMalloc((void**)&c->fsites, sizeof(int) * fo.size()), "hipMalloc(force table)");
                     hipchk(hipMemcpy(c->fsites, fo.data(), sizeof(int) * fo.size(), hipMemcpyHostToDevice),
